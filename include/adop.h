@@ -1,0 +1,231 @@
+/*
+ * adop.h -- C ABI of the MI355X (gfx950) differentiable one-pixel point
+ * rasterizer.
+ *
+ * Method: Rueckert, Franke, Stamminger, "ADOP: Approximate Differentiable
+ * One-Pixel Point Rendering", ACM TOG 41(4), 2022, Sec. 3.1.  The forward
+ * pass is the render function of Eq. render, I_l = Phi_l(C, R, t, x, n, E, tau),
+ * for pyramid layers l = 0..L-1; the backward pass returns the partials of
+ * Eq. partial (camera C, pose (R,t) in the tangent space of Eq. tangent,
+ * positions x, features tau).  The environment map E is replaced by a
+ * constant background and normals are not used.
+ *
+ * Conventions
+ *   - All device buffers are caller-owned.  Render calls never allocate
+ *     device memory; scene preparation allocates temporary device memory for
+ *     its sort and frees it before returning.
+ *   - Every call that takes a `stream` (a hipStream_t passed as void*, NULL =
+ *     the default stream) is asynchronous on that stream.  All arguments are
+ *     validated on the host before anything is enqueued; on error nothing is
+ *     enqueued and the context's last-error message says why.  A failure of
+ *     the HIP runtime is reported as ADOP_E_DEVICE with the HIP error text.
+ *   - A context is used by one host thread at a time.
+ *   - The library is built for gfx950 only.
+ *
+ * Frame layout (images, keys, counts of V views with L layers):
+ *   views follow one another; inside view v, layer l (w_l = w >> l,
+ *   h_l = h >> l) follows layer l-1.  Pixel (x, y) of layer l of view v is
+ *   element  o(v,l) + y*w_l + x  of keys and counts, where o(v,l) is given by
+ *   adop_views_layout.  Images hold C channels per pixel in channel-major
+ *   blocks: channel c of that pixel is element  C*o(v,l) + c*w_l*h_l + y*w_l + x,
+ *   so each (view, layer) is a contiguous [C][h_l][w_l] FP32 image.
+ */
+#ifndef ADOP_H
+#define ADOP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+typedef int32_t adop_status;
+#define ADOP_OK             0
+#define ADOP_E_INVALID      1   /* an argument is out of range or inconsistent */
+#define ADOP_E_UNSUPPORTED  2   /* valid request this build does not implement */
+#define ADOP_E_WORKSPACE    3   /* workspace smaller than adop_workspace_bytes */
+#define ADOP_E_DEVICE       4   /* HIP runtime error (text in adop_last_error) */
+#define ADOP_E_STATE        5   /* call out of order (e.g. graph in use) */
+
+/* feature storage types; rendering always accumulates in FP32 */
+typedef int32_t adop_dtype;
+#define ADOP_F32   0
+#define ADOP_BF16  1
+#define ADOP_F16   2
+
+#define ADOP_MAX_LAYERS     8
+#define ADOP_MAX_CHANNELS  16
+#define ADOP_MAX_VIEWS    256   /* per forward call */
+#define ADOP_MAX_VIEWS_BWD 32   /* per backward call */
+
+/* render flags */
+#define ADOP_FLAG_SPATIAL_ALL 1u  /* spatial gradient for every in-bounds point,
+                                     not only points in the blend set */
+
+/* Camera: pinhole with Brown-Conrady radial (k1,k2,k3) and tangential
+ * (p1,p2) distortion, world->camera pose x_c = R x + t (R row-major, OpenCV
+ * axes: x right, y down, z forward).  The paper names the model
+ * "Pinhole + Dist." (scene table, Sec. 4) without a formula; the projection
+ * evaluated in FP32 is
+ *   a = X/Z, b = Y/Z, r2 = a^2 + b^2, D = 1 + k1 r2 + k2 r2^2 + k3 r2^3,
+ *   x_d = a D + 2 p1 a b + p2 (r2 + 2 a^2), y_d = b D + 2 p2 a b + p1 (r2 + 2 b^2),
+ *   u0 = fx x_d + cx, v0 = fy y_d + cy,
+ * and layer l uses (u0, v0) * 2^-l (Eq. 2) rounded to the nearest integer,
+ * ties to even (Eq. round).  A point is culled when Z <= znear, when
+ * r2 > r2_max (distortion fold-over limit), or when anything is non-finite.
+ * Requirements: width, height >= 1; znear >= 0.  100 bytes. */
+typedef struct adop_camera {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float k1, k2, k3, p1, p2;
+    float znear;
+    float r2_max;
+    float R[9];
+    float t[3];
+} adop_camera;
+
+typedef struct adop_render_params {
+    int32_t layers;            /* L, 1..ADOP_MAX_LAYERS; every view needs w>>(L-1) >= 1 and h>>(L-1) >= 1 */
+    float alpha;               /* fuzzy depth test z <= (1+alpha) min_z (Eq. depthtest); >= 0 */
+    uint32_t flags;            /* ADOP_FLAG_* */
+    const float* background;   /* host, [channels] colour of empty pixels; NULL = zeros */
+} adop_render_params;
+
+/* A prepared scene (see adop_scene_prepare).  The SoA position planes and the
+ * feature array are the trainable parameters; gradients are returned in the
+ * same (prepared) order.  orig_index[i] is the caller's index of point i and
+ * breaks depth ties (smaller original index wins). */
+typedef struct adop_scene {
+    int64_t n;                 /* number of points, 0 .. 2^31-1 */
+    int32_t channels;          /* C, 1..ADOP_MAX_CHANNELS */
+    adop_dtype dtype;          /* storage type of feat */
+    const float* x;            /* device [n] */
+    const float* y;            /* device [n] */
+    const float* z;            /* device [n] */
+    const void* feat;          /* device [n][C] of dtype, 16-byte aligned */
+    const int32_t* orig_index; /* device [n] */
+} adop_scene;
+
+/* Rendered frame buffers (device, caller-owned), layout in the file comment. */
+typedef struct adop_frame {
+    float* images;             /* [C * pixels] FP32 */
+    uint64_t* keys;            /* [pixels] (bits(z) << 32 | orig_index), empty = ~0 */
+    int32_t* counts;           /* [pixels] number of blended points |Lambda| */
+    int64_t pixels;            /* must equal the total of adop_views_layout */
+} adop_frame;
+
+typedef struct adop_context adop_context;
+typedef struct adop_graph adop_graph;
+
+/* ------------------------------------------------------------ context */
+/* Create a context on HIP device `device` (makes it current on this thread).
+ * Allocates a small pinned staging ring for camera uploads. */
+adop_status adop_context_create(int32_t device, adop_context** out);
+void adop_context_destroy(adop_context* ctx);
+/* Message of the last failed call on this context ("" if none); valid until
+ * the next call on the context. */
+const char* adop_last_error(const adop_context* ctx);
+const char* adop_status_string(adop_status s);
+/* Library version string. */
+const char* adop_version(void);
+
+/* --------------------------------------------------- host-only queries */
+/* Pyramid layout of V views with L layers (no device access).  Writes the
+ * total pixel count, and if `offsets` is not NULL, o(v,l) at offsets[v*L+l]. */
+adop_status adop_views_layout(const adop_camera* cams, int32_t V, int32_t layers,
+                              int64_t* total_pixels, int64_t* offsets);
+
+/* Workspace bytes needed by render calls with C channels, V views and
+ * `pixels` pyramid pixels (the same workspace serves forward and backward). */
+size_t adop_workspace_bytes(const adop_context* ctx, int32_t channels, int32_t V,
+                            int64_t pixels);
+
+/* Bytes of the prepared feature array for n points, C channels, dtype. */
+size_t adop_feature_bytes(int64_t n, int32_t channels, adop_dtype dtype);
+
+/* ------------------------------------------------------- scene upload */
+/* Reorder a point cloud for rendering (Sec. 3.1, "Implementation Details":
+ * the blocked Morton shuffle).  Points are sorted by a 63-bit Morton code
+ * over their bounding box, cut into 8 contiguous segments (one per XCD), and
+ * blocks of `block` points (a multiple of 256; 0 = 1024) are shuffled inside
+ * each segment with a permutation drawn from `seed`.
+ *   pos       device [n][3] FP32, caller's order
+ *   feat      device [n][C] of dtype, caller's order
+ *   x,y,z     device [n] FP32 outputs (SoA positions)
+ *   feat_out  device [n][C] of dtype output
+ *   orig_index device [n] output: caller's index of each prepared point
+ * Allocates and frees temporary device memory (about 24 bytes per point);
+ * synchronises `stream` before returning. */
+adop_status adop_scene_prepare(adop_context* ctx, const float* pos, const void* feat,
+                               int64_t n, int32_t channels, adop_dtype dtype,
+                               int32_t block, uint64_t seed,
+                               float* x, float* y, float* z, void* feat_out,
+                               int32_t* orig_index, void* stream);
+
+/* ---------------------------------------------------------- rendering */
+/* Forward pass (Eqs. render, round, boundscheck, depthtest, blend): the
+ * depth pass writes per-pixel keys with a 64-bit atomic minimum, the
+ * accumulation pass sums the features of every point passing the fuzzy
+ * depth test and counts them, and the normalisation writes the means (or the
+ * background) into `frame->images`.  `cams` is a host array of V cameras,
+ * staged to the workspace by the call.  Keys and counts are exact (they do
+ * not depend on the order of floating-point operations). */
+adop_status adop_render_forward(adop_context* ctx, const adop_scene* scene,
+                                const adop_camera* cams, int32_t V,
+                                const adop_render_params* params,
+                                const adop_frame* frame,
+                                void* workspace, size_t workspace_bytes, void* stream);
+
+/* Backward pass (Eqs. partial, induce, gradp, spatialderiv, tangent).
+ * Inputs: the frame written by adop_render_forward with the same scene,
+ * cameras and params, and grad_images = dL/dI in the image layout.  Outputs
+ * (device, overwritten):
+ *   dfeat [n][C] FP32   -- derivative of Eq. blend (points in the blend set)
+ *   dpos  [3][n] FP32   -- dL/dx, dL/dy, dL/dz from the approximate spatial
+ *                          gradient chained through the projection
+ *   dpose [V][6] FP64   -- dL/dxi, xi = (rho, omega) applied as exp(xi)*(R,t)
+ *                          on the left, at xi = 0
+ *   dintr [V][9] FP64   -- dL/d(fx, fy, cx, cy, k1, k2, k3, p1, p2)
+ * The FP64 sums are reduced in a fixed order (run-to-run deterministic). */
+adop_status adop_render_backward(adop_context* ctx, const adop_scene* scene,
+                                 const adop_camera* cams, int32_t V,
+                                 const adop_render_params* params,
+                                 const adop_frame* frame, const float* grad_images,
+                                 float* dfeat, float* dpos, double* dpose, double* dintr,
+                                 void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------ per-kernel timing */
+/* When enabled, every kernel a render call enqueues is bracketed by HIP
+ * events recorded on the same stream.  adop_timing_read waits for the
+ * recorded events, writes for each kernel id k < nkernels the summed
+ * duration in milliseconds and the number of launches since the previous
+ * read, and clears the records.  Kernel ids: 0 k_clear, 1 k_depth,
+ * 2 k_accum, 3 k_normalize, 4 k_pack, 5 k_backward, 6 k_reduce.  Not used
+ * inside captured graphs. */
+#define ADOP_TIMING_KERNELS 7
+adop_status adop_timing_enable(adop_context* ctx, int32_t on);
+adop_status adop_timing_read(adop_context* ctx, int32_t nkernels, double* total_ms, int64_t* launches);
+const char* adop_timing_kernel_name(int32_t kernel);
+
+/* ------------------------------------------- captured forward (serving) */
+/* Capture the forward pass for V cameras of fixed sizes into a HIP graph
+ * bound to the given scene, frame and workspace.  The graph holds kernels
+ * only; adop_forward_graph_launch stages new cameras (same widths and
+ * heights as `cams`) into the workspace and replays it.  Launches of one
+ * graph are serialised: a launch waits until the previous launch's camera
+ * copy has been consumed. */
+adop_status adop_forward_graph_create(adop_context* ctx, const adop_scene* scene,
+                                      const adop_camera* cams, int32_t V,
+                                      const adop_render_params* params,
+                                      const adop_frame* frame,
+                                      void* workspace, size_t workspace_bytes,
+                                      adop_graph** out);
+adop_status adop_forward_graph_launch(adop_graph* g, const adop_camera* cams, void* stream);
+void adop_graph_destroy(adop_graph* g);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADOP_H */

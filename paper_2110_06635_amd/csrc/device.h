@@ -1,0 +1,276 @@
+// Device-side building blocks of the one-pixel point rasterizer (gfx950).
+//
+// - ViewRec: the per-view record the kernels read (camera + pyramid layout).
+// - project(): the FP32 projection of Sec. 3.1 Eq. 2 with pinhole +
+//   Brown-Conrady distortion, written with explicit fused multiply-adds so
+//   that the result does not depend on compiler contraction (the library is
+//   also built with -ffp-contract=off).  Depth keys and pixel choices are
+//   bit-exact functions of this arithmetic.
+// - wave64 helpers built on DPP row shifts / row broadcasts and ballots.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace adop {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;          // threads per workgroup for point kernels
+constexpr int kMaxLayers = 8;
+constexpr int kXcds = 8;             // MI355X: 8 XCDs, workgroups dispatched round-robin
+constexpr int kMaxViewsBwd = 32;
+
+// 256-byte per-view record staged into the workspace by the host.
+struct alignas(16) ViewRec {
+    float fx, fy, cx, cy;
+    float k1, k2, k3, p1;
+    float p2, znear, r2max, pad0;
+    float R[9];
+    float t[3];
+    int32_t w, h, L, pad1;
+    int32_t lw[kMaxLayers];
+    int32_t lh[kMaxLayers];
+    uint32_t base[kMaxLayers];       // first pixel of layer l of this view in the frame
+    float pad2[12];
+};
+static_assert(sizeof(ViewRec) == 256, "ViewRec must be 256 bytes");
+
+// Layer scale 2^-l as an exact constant.
+__device__ __forceinline__ float layer_scale(int l) {
+    return __int_as_float((127 - l) << 23);
+}
+
+struct Proj {
+    float X, Y, Z;        // camera-space position
+    float a, b, r2, D;    // normalised coordinates and radial factor
+    float xd, yd;         // distorted normalised coordinates
+    float u0, v0;         // layer-0 pixel coordinates
+    bool ok;
+};
+
+// x_c = R x + t, a = X/Z, b = Y/Z, r2 = a^2 + b^2,
+// D = 1 + k1 r2 + k2 r2^2 + k3 r2^3,
+// x_d = a D + 2 p1 a b + p2 (r2 + 2a^2), y_d = b D + 2 p2 a b + p1 (r2 + 2b^2),
+// u0 = fx x_d + cx, v0 = fy y_d + cy.
+__device__ __forceinline__ Proj project(const ViewRec& c, float x, float y, float z) {
+    Proj p;
+    float X = __fmaf_rn(c.R[0], x, __fmaf_rn(c.R[1], y, __fmaf_rn(c.R[2], z, c.t[0])));
+    float Y = __fmaf_rn(c.R[3], x, __fmaf_rn(c.R[4], y, __fmaf_rn(c.R[5], z, c.t[1])));
+    float Z = __fmaf_rn(c.R[6], x, __fmaf_rn(c.R[7], y, __fmaf_rn(c.R[8], z, c.t[2])));
+    float a = __fdiv_rn(X, Z);
+    float b = __fdiv_rn(Y, Z);
+    float ab = __fmul_rn(a, b);
+    float bb = __fmul_rn(b, b);
+    float r2 = __fmaf_rn(a, a, bb);
+    float D = __fmaf_rn(r2, __fmaf_rn(r2, __fmaf_rn(r2, c.k3, c.k2), c.k1), 1.0f);
+    float tx = __fmul_rn(c.p2, __fmaf_rn(__fadd_rn(a, a), a, r2));
+    float ty = __fmul_rn(c.p1, __fmaf_rn(__fadd_rn(b, b), b, r2));
+    float xd = __fmaf_rn(a, D, __fmaf_rn(__fadd_rn(c.p1, c.p1), ab, tx));
+    float yd = __fmaf_rn(b, D, __fmaf_rn(__fadd_rn(c.p2, c.p2), ab, ty));
+    p.u0 = __fmaf_rn(c.fx, xd, c.cx);
+    p.v0 = __fmaf_rn(c.fy, yd, c.cy);
+    p.X = X; p.Y = Y; p.Z = Z;
+    p.a = a; p.b = b; p.r2 = r2; p.D = D; p.xd = xd; p.yd = yd;
+    p.ok = (Z > c.znear) && (r2 <= c.r2max) && __builtin_isfinite(p.u0) && __builtin_isfinite(p.v0);
+    return p;
+}
+
+// Pixel of layer l (Eq. round + Eq. boundscheck): rint(u0 * 2^-l), in
+// [0,w_l) x [0,h_l).  Returns the frame pixel index in *pix.
+__device__ __forceinline__ bool layer_pixel(const ViewRec& c, int l, float u0, float v0,
+                                            int& px, int& py, uint32_t& pix) {
+    float s = layer_scale(l);
+    float fx = __builtin_rintf(__fmul_rn(u0, s));
+    float fy = __builtin_rintf(__fmul_rn(v0, s));
+    int lw = c.lw[l], lh = c.lh[l];
+    bool in = fx >= 0.0f && fx < (float)lw && fy >= 0.0f && fy < (float)lh;
+    px = in ? (int)fx : 0;
+    py = in ? (int)fy : 0;
+    pix = c.base[l] + (uint32_t)py * (uint32_t)lw + (uint32_t)px;
+    return in;
+}
+
+// ----------------------------------------------------------------------------
+// wave64 helpers
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+template <int CTRL, int ROWMASK, bool BOUND>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t old, uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWMASK, 0xf, BOUND);
+}
+
+// Sum over all 64 lanes (every lane must be active); the total is returned
+// to every lane.  Row shifts 1,2,4,8 build row sums in lane 15 of each row,
+// row broadcasts 15 and 31 carry them to lane 63.
+__device__ __forceinline__ float wave_sum(float v) {
+    v += __uint_as_float(dpp_u32<0x111, 0xf, true>(0u, __float_as_uint(v)));
+    v += __uint_as_float(dpp_u32<0x112, 0xf, true>(0u, __float_as_uint(v)));
+    v += __uint_as_float(dpp_u32<0x114, 0xf, true>(0u, __float_as_uint(v)));
+    v += __uint_as_float(dpp_u32<0x118, 0xf, true>(0u, __float_as_uint(v)));
+    v += __uint_as_float(dpp_u32<0x142, 0xa, false>(0u, __float_as_uint(v)));
+    v += __uint_as_float(dpp_u32<0x143, 0xc, false>(0u, __float_as_uint(v)));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+template <int CTRL, int ROWMASK, bool BOUND>
+__device__ __forceinline__ double dpp_f64(double v) {
+    uint64_t u = (uint64_t)__double_as_longlong(v);
+    uint32_t lo = dpp_u32<CTRL, ROWMASK, BOUND>(0u, (uint32_t)u);
+    uint32_t hi = dpp_u32<CTRL, ROWMASK, BOUND>(0u, (uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// FP64 sum over all 64 lanes (fixed order), result valid in lane 63 and
+// returned to every lane via readlane.
+__device__ __forceinline__ double wave_sum_f64(double v) {
+    v += dpp_f64<0x111, 0xf, true>(v);
+    v += dpp_f64<0x112, 0xf, true>(v);
+    v += dpp_f64<0x114, 0xf, true>(v);
+    v += dpp_f64<0x118, 0xf, true>(v);
+    v += dpp_f64<0x142, 0xa, false>(v);
+    v += dpp_f64<0x143, 0xc, false>(v);
+    uint64_t u = (uint64_t)__double_as_longlong(v);
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, 63);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Minimum of a u64 over all 64 lanes (every lane active), broadcast.
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#define ADOP_MIN_STEP(CTRL, RM)                                                   \
+    {                                                                             \
+        uint32_t lo = dpp_u32<CTRL, RM, false>(0xffffffffu, (uint32_t)v);         \
+        uint32_t hi = dpp_u32<CTRL, RM, false>(0xffffffffu, (uint32_t)(v >> 32)); \
+        uint64_t o = ((uint64_t)hi << 32) | lo;                                   \
+        v = o < v ? o : v;                                                        \
+    }
+    ADOP_MIN_STEP(0x111, 0xf)
+    ADOP_MIN_STEP(0x112, 0xf)
+    ADOP_MIN_STEP(0x114, 0xf)
+    ADOP_MIN_STEP(0x118, 0xf)
+    ADOP_MIN_STEP(0x142, 0xa)
+    ADOP_MIN_STEP(0x143, 0xc)
+#undef ADOP_MIN_STEP
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t load_relaxed_u64(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void atomic_min_u64(uint64_t* p, uint64_t v) {
+    __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void atomic_add_f32(float* p, float v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void atomic_add_i32(int32_t* p, int32_t v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ----------------------------------------------------------------------------
+// feature storage
+// ----------------------------------------------------------------------------
+struct F32 { using T = float; static constexpr int bytes = 4; };
+struct BF16 { using T = uint16_t; static constexpr int bytes = 2; };
+struct F16 { using T = uint16_t; static constexpr int bytes = 2; };
+
+template <typename S> __device__ __forceinline__ float widen(typename S::T v);
+template <> __device__ __forceinline__ float widen<F32>(float v) { return v; }
+template <> __device__ __forceinline__ float widen<BF16>(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
+template <> __device__ __forceinline__ float widen<F16>(uint16_t v) {
+    _Float16 h = __builtin_bit_cast(_Float16, v);
+    return (float)h;
+}
+
+// Load the C features of point i (row-major [n][C]) widened to FP32.
+template <int C, typename S>
+__device__ __forceinline__ void load_feat(const void* feat, int64_t i, float (&f)[C]) {
+    using T = typename S::T;
+    const T* p = reinterpret_cast<const T*>(feat) + i * C;
+    constexpr int bytes = C * S::bytes;
+    if constexpr (bytes % 16 == 0) {
+        const uint4* q = reinterpret_cast<const uint4*>(p);
+        T tmp[C];
+#pragma unroll
+        for (int k = 0; k < bytes / 16; ++k) reinterpret_cast<uint4*>(tmp)[k] = q[k];
+#pragma unroll
+        for (int c = 0; c < C; ++c) f[c] = widen<S>(tmp[c]);
+    } else if constexpr (bytes % 8 == 0) {
+        const uint2* q = reinterpret_cast<const uint2*>(p);
+        T tmp[C];
+#pragma unroll
+        for (int k = 0; k < bytes / 8; ++k) reinterpret_cast<uint2*>(tmp)[k] = q[k];
+#pragma unroll
+        for (int c = 0; c < C; ++c) f[c] = widen<S>(tmp[c]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) f[c] = widen<S>(p[c]);
+    }
+}
+
+template <int C>
+__device__ __forceinline__ void store_f32_row(float* out, int64_t i, const float (&f)[C]) {
+    float* p = out + i * C;
+    if constexpr (C % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < C / 4; ++k)
+            reinterpret_cast<float4*>(p)[k] = make_float4(f[4 * k], f[4 * k + 1], f[4 * k + 2], f[4 * k + 3]);
+    } else if constexpr (C % 2 == 0) {
+#pragma unroll
+        for (int k = 0; k < C / 2; ++k) reinterpret_cast<float2*>(p)[k] = make_float2(f[2 * k], f[2 * k + 1]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) p[c] = f[c];
+    }
+}
+
+// Per-pixel record the backward pass gathers: upstream gradient G (C floats),
+// gdot = <G, I> (or <G, background> for an empty pixel), the front depth
+// min_z as float bits, and the blend count n.
+template <int C> struct PackLayout {
+    static constexpr int used = C + 3;
+    static constexpr int stride = (used + 3) / 4 * 4;   // floats, multiple of 4
+    static constexpr int gdot = C, minz = C + 1, count = C + 2;
+};
+
+// Chunk mapping of point kernels: workgroup b runs on XCD b % 8; the points
+// are split into 8 contiguous segments (segment boundaries rounded down to
+// `seg_align` points) and the workgroups of XCD x stride over the chunks of
+// segment x, so that each XCD renders one region of the Morton-ordered cloud
+// and its L2 keeps that region's pixels.
+struct ChunkMap {
+    int64_t n;
+    int64_t seg_lo, seg_hi;   // this workgroup's segment, in points
+    int64_t first, step;      // first chunk start and stride, in points
+};
+
+__device__ __forceinline__ int64_t segment_bound(int64_t n, int x, int64_t align) {
+    if (x >= kXcds) return n;
+    int64_t b = (n * x) / kXcds;
+    return b / align * align;
+}
+
+__device__ __forceinline__ ChunkMap chunk_map(int64_t n, int64_t chunk, int64_t align) {
+    ChunkMap m;
+    m.n = n;
+    int g = (int)gridDim.x;
+    int b = (int)blockIdx.x;
+    int x = b % kXcds;
+    int per = g / kXcds;            // grid is a multiple of 8
+    int k = b / kXcds;
+    m.seg_lo = segment_bound(n, x, align);
+    m.seg_hi = segment_bound(n, x + 1, align);
+    m.first = m.seg_lo + (int64_t)k * chunk;
+    m.step = (int64_t)per * chunk;
+    return m;
+}
+
+}  // namespace adop

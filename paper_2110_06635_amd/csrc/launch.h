@@ -1,0 +1,84 @@
+// Host-side launch interface between the C-ABI layer (api.cpp) and the
+// kernels (render.hip, scene.hip).  Plain structs of device pointers and sizes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace adop {
+
+struct ViewRec;
+
+// Points are processed in 8 segments (one per XCD) whose boundaries are
+// multiples of this many points; scene preparation shuffles blocks inside
+// the same segments.
+constexpr int64_t kSegAlign = 1024;
+
+// Optional per-kernel timing: the launchers call fn(self, kernel, 0, stream)
+// before and fn(self, kernel, 1, stream) after each kernel they enqueue.
+enum KernelId { kKClear = 0, kKDepth, kKAccum, kKNormalize, kKPack, kKBackward, kKReduce, kKernelCount };
+struct Timer {
+    void (*fn)(void* self, int kernel, int end, hipStream_t st) = nullptr;
+    void* self = nullptr;
+    void mark(int k, int end, hipStream_t st) const {
+        if (fn) fn(self, k, end, st);
+    }
+};
+
+struct FwdArgs {
+    int dtype, C, V, L, cus;
+    int64_t n, pixels, max_layer_pixels;
+    float fa;
+    const float *x, *y, *z;
+    const void* feat;
+    const int32_t* orig;
+    const ViewRec* views;
+    uint64_t* keys;
+    int32_t* counts;
+    float* sums;       // workspace [pixels][C]
+    float* images;
+    const float* background;   // host [C] or null
+    Timer timer;
+};
+
+struct BwdArgs {
+    int dtype, C, V, L, groups;
+    uint32_t flags;
+    int64_t n, pixels, max_layer_pixels;
+    float fa;
+    const float *x, *y, *z;
+    const void* feat;
+    const ViewRec* views;
+    const uint64_t* keys;
+    const int32_t* counts;
+    const float* images;
+    const float* grad;
+    float* pack;       // workspace [pixels][stride]
+    double* partials;  // workspace [groups][V][16]
+    float* dfeat;
+    float* dpos;
+    double* dpose;
+    double* dintr;
+    const float* background;
+    Timer timer;
+};
+
+hipError_t launch_forward(const FwdArgs& a, hipStream_t st);
+hipError_t launch_backward(const BwdArgs& a, hipStream_t st);
+int backward_points_per_group(int C);
+inline int pack_stride(int C) { return (C + 3 + 3) / 4 * 4; }
+
+struct PrepArgs {
+    int64_t n;
+    int C, dtype, block;
+    uint64_t seed;
+    const float* pos;
+    const void* feat;
+    float *x, *y, *z;
+    void* feat_out;
+    int32_t* orig;
+};
+// Returns hipSuccess or the first HIP error; allocates temporaries.
+hipError_t scene_prepare(const PrepArgs& a, hipStream_t st);
+
+}  // namespace adop

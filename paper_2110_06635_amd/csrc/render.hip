@@ -1,0 +1,519 @@
+// HIP kernels of the one-pixel point rasterizer (ADOP Sec. 3.1) for gfx950.
+//
+// Forward (three passes over the points, as in "Implementation Details"):
+//   k_clear      keys := empty, counts := 0, sums := 0
+//   k_depth      project every point into every view and layer, 64-bit
+//                atomic minimum of (depth bits << 32 | original index)
+//   k_accum      fuzzy depth test z <= (1+alpha) min_z (Eq. depthtest),
+//                FP32 atomic sums of the features and an integer count
+//   k_normalize  mean of the blend set or the background (Eq. blend)
+// Backward:
+//   k_pack       per-pixel record {G, <G,I>, min_z, n} for the gathers
+//   k_backward   re-render every point (the blend sets are not stored),
+//                feature gradient, approximate spatial gradient (Eqs. induce,
+//                gradp, spatialderiv), chain to positions, pose (Eq. tangent)
+//                and intrinsics; per-point terms in FP32, pose/intrinsics
+//                sums in FP64 with a fixed reduction order
+//   k_reduce     fixed-order FP64 sum of the per-workgroup partials
+//
+// Contention handling: a wave whose active lanes all hit one pixel reduces
+// in registers (DPP) and issues one atomic; otherwise lanes test the current
+// key before the atomic minimum (keys only decrease, so a stale read can only
+// let an unnecessary atomic through).
+#include "device.h"
+#include "launch.h"
+
+namespace adop {
+
+// ---------------------------------------------------------------------------
+// forward
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_clear(uint64_t* __restrict__ keys, int32_t* __restrict__ counts,
+                                               float* __restrict__ sums, int64_t pixels, int64_t nsum) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < pixels; i += stride) {
+        keys[i] = ~0ull;
+        counts[i] = 0;
+    }
+    float4* s4 = reinterpret_cast<float4*>(sums);
+    int64_t n4 = nsum / 4;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride)
+        s4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int64_t i = n4 * 4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nsum; i += stride)
+        sums[i] = 0.f;
+}
+
+__device__ __forceinline__ void depth_update(bool in, uint32_t pix, uint64_t key, uint64_t* __restrict__ keys) {
+    uint64_t m = ballot(in);
+    if (m == 0) return;
+    int leader = __builtin_ctzll(m);
+    uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pix, leader);
+    if (ballot(in && pix != p0) == 0) {
+        uint64_t k = wave_min_u64(in ? key : ~0ull);
+        if (lane_id() == leader) {
+            uint64_t cur = load_relaxed_u64(keys + p0);
+            if (k < cur) atomic_min_u64(keys + p0, k);
+        }
+    } else if (in) {
+        uint64_t cur = load_relaxed_u64(keys + pix);
+        if (key < cur) atomic_min_u64(keys + pix, key);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_depth(const float* __restrict__ xs, const float* __restrict__ ys,
+                                               const float* __restrict__ zs, const int32_t* __restrict__ orig,
+                                               int64_t n, const ViewRec* __restrict__ views, int V, int L,
+                                               uint64_t* __restrict__ keys) {
+    ChunkMap m = chunk_map(n, kBlock, kSegAlign);
+    for (int64_t base = m.first; base < m.seg_hi; base += m.step) {
+        int64_t i = base + threadIdx.x;
+        bool live = i < m.seg_hi;
+        float x = 0.f, y = 0.f, z = 0.f;
+        uint32_t oi = 0;
+        if (live) {
+            x = xs[i];
+            y = ys[i];
+            z = zs[i];
+            oi = (uint32_t)orig[i];
+        }
+        for (int v = 0; v < V; ++v) {
+            const ViewRec& c = views[v];
+            Proj p = project(c, x, y, z);
+            bool ok = live && p.ok;
+            uint64_t key = ((uint64_t)__float_as_uint(p.Z) << 32) | oi;
+            for (int l = 0; l < L; ++l) {
+                int px = 0, py = 0;
+                uint32_t pix = 0;
+                bool in = ok && layer_pixel(c, l, p.u0, p.v0, px, py, pix);
+                depth_update(in, pix, key, keys);
+            }
+        }
+    }
+}
+
+template <int C>
+__device__ __forceinline__ void accum_update(bool pass, uint32_t pix, const float (&f)[C],
+                                             float* __restrict__ sums, int32_t* __restrict__ counts) {
+    uint64_t m = ballot(pass);
+    if (m == 0) return;
+    int leader = __builtin_ctzll(m);
+    uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pix, leader);
+    if (ballot(pass && pix != p0) == 0) {
+        float s[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) s[c] = wave_sum(pass ? f[c] : 0.0f);
+        if (lane_id() == leader) {
+            float* dst = sums + (uint64_t)p0 * C;
+#pragma unroll
+            for (int c = 0; c < C; ++c) atomic_add_f32(dst + c, s[c]);
+            atomic_add_i32(counts + p0, (int32_t)__builtin_popcountll(m));
+        }
+    } else if (pass) {
+        float* dst = sums + (uint64_t)pix * C;
+#pragma unroll
+        for (int c = 0; c < C; ++c) atomic_add_f32(dst + c, f[c]);
+        atomic_add_i32(counts + pix, 1);
+    }
+}
+
+template <int C, typename S>
+__global__ void __launch_bounds__(256) k_accum(const float* __restrict__ xs, const float* __restrict__ ys,
+                                               const float* __restrict__ zs, const void* __restrict__ feat,
+                                               int64_t n, const ViewRec* __restrict__ views, int V, int L,
+                                               float fa, const uint32_t* __restrict__ keys32,
+                                               float* __restrict__ sums, int32_t* __restrict__ counts) {
+    ChunkMap m = chunk_map(n, kBlock, kSegAlign);
+    for (int64_t base = m.first; base < m.seg_hi; base += m.step) {
+        int64_t i = base + threadIdx.x;
+        bool live = i < m.seg_hi;
+        float x = 0.f, y = 0.f, z = 0.f;
+        float f[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) f[c] = 0.f;
+        if (live) {
+            x = xs[i];
+            y = ys[i];
+            z = zs[i];
+            load_feat<C, S>(feat, i, f);
+        }
+        for (int v = 0; v < V; ++v) {
+            const ViewRec& c = views[v];
+            Proj p = project(c, x, y, z);
+            bool ok = live && p.ok;
+            for (int l = 0; l < L; ++l) {
+                int px = 0, py = 0;
+                uint32_t pix = 0;
+                bool in = ok && layer_pixel(c, l, p.u0, p.v0, px, py, pix);
+                bool pass = false;
+                if (in) {
+                    float minz = __uint_as_float(keys32[2 * (uint64_t)pix + 1]);
+                    pass = p.Z <= __fmul_rn(minz, fa);
+                }
+                accum_update<C>(pass, pix, f, sums, counts);
+            }
+        }
+    }
+}
+
+struct Background {
+    float v[16];
+};
+
+template <int C>
+__global__ void __launch_bounds__(256) k_normalize(const ViewRec* __restrict__ views, int L,
+                                                   const float* __restrict__ sums,
+                                                   const int32_t* __restrict__ counts,
+                                                   float* __restrict__ images, Background bg) {
+    int vl = blockIdx.y;
+    int v = vl / L, l = vl - (vl / L) * L;
+    const ViewRec& c = views[v];
+    int64_t npx = (int64_t)c.lw[l] * c.lh[l];
+    uint64_t base = c.base[l];
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < npx; j += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t p = base + (uint64_t)j;
+        int32_t k = counts[p];
+        const float* s = sums + p * C;
+        float* out = images + (uint64_t)C * base + (uint64_t)j;
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch) {
+            float val = k > 0 ? __fdiv_rn(s[ch], (float)k) : bg.v[ch];
+            out[(uint64_t)ch * (uint64_t)npx] = val;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// backward
+// ---------------------------------------------------------------------------
+
+template <int C>
+__global__ void __launch_bounds__(256) k_pack(const ViewRec* __restrict__ views, int L,
+                                              const uint64_t* __restrict__ keys,
+                                              const int32_t* __restrict__ counts,
+                                              const float* __restrict__ images,
+                                              const float* __restrict__ grad,
+                                              float* __restrict__ pack, Background bg) {
+    using PL = PackLayout<C>;
+    int vl = blockIdx.y;
+    int v = vl / L, l = vl - (vl / L) * L;
+    const ViewRec& c = views[v];
+    int64_t npx = (int64_t)c.lw[l] * c.lh[l];
+    uint64_t base = c.base[l];
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < npx; j += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t p = base + (uint64_t)j;
+        int32_t k = counts[p];
+        uint32_t minz = (uint32_t)(keys[p] >> 32);
+        const float* gi = grad + (uint64_t)C * base + (uint64_t)j;
+        const float* ii = images + (uint64_t)C * base + (uint64_t)j;
+        float rec[PL::stride];
+        float gdot = 0.f;
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch) {
+            float g = gi[(uint64_t)ch * (uint64_t)npx];
+            float I = k > 0 ? ii[(uint64_t)ch * (uint64_t)npx] : bg.v[ch];
+            rec[ch] = g;
+            gdot = __fmaf_rn(g, I, gdot);
+        }
+        rec[PL::gdot] = gdot;
+        rec[PL::minz] = __uint_as_float(minz);
+        rec[PL::count] = __int_as_float(k);
+#pragma unroll
+        for (int q = PL::used; q < PL::stride; ++q) rec[q] = 0.f;
+        float4* dst = reinterpret_cast<float4*>(pack + p * PL::stride);
+#pragma unroll
+        for (int q = 0; q < PL::stride / 4; ++q)
+            dst[q] = make_float4(rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], rec[4 * q + 3]);
+    }
+}
+
+// <G(q), dI> for the point virtually moved into neighbour q (Eq. spatialderiv):
+// empty q -> tau - b; point hidden behind q (z > (1+alpha) min_z(q)) -> 0;
+// point in front (z (1+alpha) < min_z(q)) -> tau - I(q); otherwise the point
+// joins q's blend set -> (tau - I(q)) / (n+1).  With gdot = <G, I(q)> (or
+// <G, b>), every case is factor * (<G(q), tau> - gdot).
+template <int C>
+__device__ __forceinline__ float induced(const float* __restrict__ pack, uint64_t q, float Z, float fa,
+                                         const float (&tau)[C]) {
+    using PL = PackLayout<C>;
+    const float* r = pack + q * PL::stride;
+    float rec[PL::stride];
+#pragma unroll
+    for (int k = 0; k < PL::stride / 4; ++k) {
+        float4 t4 = reinterpret_cast<const float4*>(r)[k];
+        rec[4 * k] = t4.x;
+        rec[4 * k + 1] = t4.y;
+        rec[4 * k + 2] = t4.z;
+        rec[4 * k + 3] = t4.w;
+    }
+    int nq = __float_as_int(rec[PL::count]);
+    float mq = rec[PL::minz];
+    float dot = 0.f;
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch) dot = __fmaf_rn(rec[ch], tau[ch], dot);
+    float t = dot - rec[PL::gdot];
+    float factor;
+    if (nq == 0) {
+        factor = 1.0f;
+    } else if (Z > __fmul_rn(mq, fa)) {
+        factor = 0.0f;
+    } else if (__fmul_rn(Z, fa) < mq) {
+        factor = 1.0f;
+    } else {
+        factor = __frcp_rn((float)(nq + 1));
+    }
+    return factor * t;
+}
+
+template <int C, typename S, int PPL>
+__global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, const float* __restrict__ ys,
+                                                  const float* __restrict__ zs, const void* __restrict__ feat,
+                                                  int64_t n, const ViewRec* __restrict__ views, int V, int L,
+                                                  float fa, uint32_t flags, const float* __restrict__ pack,
+                                                  float* __restrict__ dfeat, float* __restrict__ dpos,
+                                                  double* __restrict__ partials) {
+    using PL = PackLayout<C>;
+    extern __shared__ double acc_lds[];     // [4 waves][V][16]
+    const int wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    for (int j = threadIdx.x; j < 4 * V * 16; j += blockDim.x) acc_lds[j] = 0.0;
+    __syncthreads();
+    const bool spatial_all = (flags & 1u) != 0;
+
+    ChunkMap m = chunk_map(n, (int64_t)kBlock * PPL, kSegAlign);
+    for (int64_t base = m.first; base < m.seg_hi; base += m.step) {
+        const int64_t wbase = base + (int64_t)wave * kWave * PPL;
+        float px_[PPL], py_[PPL], pz_[PPL];
+        float tau[PPL][C], dt[PPL][C], dp[PPL][3];
+        bool live[PPL];
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+            int64_t i = wbase + (int64_t)k * kWave + lane;
+            live[k] = i < m.seg_hi;
+            px_[k] = py_[k] = pz_[k] = 0.f;
+#pragma unroll
+            for (int c = 0; c < C; ++c) { tau[k][c] = 0.f; dt[k][c] = 0.f; }
+            dp[k][0] = dp[k][1] = dp[k][2] = 0.f;
+            if (live[k]) {
+                px_[k] = xs[i];
+                py_[k] = ys[i];
+                pz_[k] = zs[i];
+                load_feat<C, S>(feat, i, tau[k]);
+            }
+        }
+        for (int v = 0; v < V; ++v) {
+            const ViewRec& c = views[v];
+            double acc[15];
+#pragma unroll
+            for (int t = 0; t < 15; ++t) acc[t] = 0.0;
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) {
+                Proj p = project(c, px_[k], py_[k], pz_[k]);
+                if (!(live[k] && p.ok)) continue;
+                float gu = 0.f, gv = 0.f;
+                for (int l = 0; l < L; ++l) {
+                    int qx = 0, qy = 0;
+                    uint32_t pix = 0;
+                    if (!layer_pixel(c, l, p.u0, p.v0, qx, qy, pix)) continue;
+                    const float* r = pack + (uint64_t)pix * PL::stride;
+                    float minz = r[PL::minz];
+                    bool vis = p.Z <= __fmul_rn(minz, fa);
+                    if (vis) {
+                        float inv = __frcp_rn((float)__float_as_int(r[PL::count]));
+#pragma unroll
+                        for (int ch = 0; ch < C; ++ch) dt[k][ch] = __fmaf_rn(r[ch], inv, dt[k][ch]);
+                    }
+                    if (!(vis || spatial_all)) continue;
+                    const int lw = c.lw[l], lh = c.lh[l];
+                    float tr = qx + 1 < lw ? induced<C>(pack, (uint64_t)pix + 1, p.Z, fa, tau[k]) : 0.f;
+                    float tl = qx > 0 ? induced<C>(pack, (uint64_t)pix - 1, p.Z, fa, tau[k]) : 0.f;
+                    float td = qy + 1 < lh ? induced<C>(pack, (uint64_t)pix + lw, p.Z, fa, tau[k]) : 0.f;
+                    float tu = qy > 0 ? induced<C>(pack, (uint64_t)pix - lw, p.Z, fa, tau[k]) : 0.f;
+                    const float s = 0.5f * layer_scale(l);
+                    gu = __fmaf_rn(tr - tl, s, gu);
+                    gv = __fmaf_rn(td - tu, s, gv);
+                }
+                if (gu == 0.f && gv == 0.f) continue;
+                any = true;
+                // chain through the projection (FP32 per-point terms)
+                const float a = p.a, b = p.b, r2 = p.r2, D = p.D;
+                const float Dp = __fmaf_rn(r2, __fmaf_rn(r2, 3.0f * c.k3, 2.0f * c.k2), c.k1);
+                const float xa = D + 2.0f * a * a * Dp + 2.0f * c.p1 * b + 6.0f * c.p2 * a;
+                const float xb = 2.0f * a * b * Dp + 2.0f * c.p1 * a + 2.0f * c.p2 * b;
+                const float yb = D + 2.0f * b * b * Dp + 6.0f * c.p1 * b + 2.0f * c.p2 * a;
+                const float gux = gu * c.fx, gvy = gv * c.fy;
+                const float ga = gux * xa + gvy * xb;
+                const float gb = gux * xb + gvy * yb;
+                const float iz = 1.0f / p.Z;
+                const float gcx = ga * iz, gcy = gb * iz, gcz = -(a * ga + b * gb) * iz;
+                dp[k][0] += c.R[0] * gcx + c.R[3] * gcy + c.R[6] * gcz;
+                dp[k][1] += c.R[1] * gcx + c.R[4] * gcy + c.R[7] * gcz;
+                dp[k][2] += c.R[2] * gcx + c.R[5] * gcy + c.R[8] * gcz;
+                const float au = gux * a + gvy * b;
+                const float r4 = r2 * r2;
+                float term[15] = {gcx, gcy, gcz,
+                                  p.Y * gcz - p.Z * gcy, p.Z * gcx - p.X * gcz, p.X * gcy - p.Y * gcx,
+                                  gu * p.xd, gv * p.yd, gu, gv, au * r2, au * r4, au * r4 * r2,
+                                  gux * 2.0f * a * b + gvy * (r2 + 2.0f * b * b),
+                                  gux * (r2 + 2.0f * a * a) + gvy * 2.0f * a * b};
+#pragma unroll
+                for (int t = 0; t < 15; ++t) acc[t] += (double)term[t];
+            }
+            if (ballot(any) != 0) {
+#pragma unroll
+                for (int t = 0; t < 15; ++t) {
+                    double s = wave_sum_f64(acc[t]);
+                    if (lane == 0) acc_lds[(wave * V + v) * 16 + t] += s;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+            if (!live[k]) continue;
+            int64_t i = wbase + (int64_t)k * kWave + lane;
+            store_f32_row<C>(dfeat, i, dt[k]);
+            dpos[i] = dp[k][0];
+            dpos[n + i] = dp[k][1];
+            dpos[2 * n + i] = dp[k][2];
+        }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < V * 16; j += blockDim.x) {
+        double s = 0.0;
+        for (int w = 0; w < 4; ++w) s += acc_lds[w * V * 16 + j];
+        partials[(uint64_t)blockIdx.x * V * 16 + j] = s;
+    }
+}
+
+// Fixed-order FP64 sum over workgroup partials; block v writes view v.
+__global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ partials, int groups, int V,
+                                                double* __restrict__ dpose, double* __restrict__ dintr) {
+    __shared__ double red[256][16];
+    int v = blockIdx.x;
+    double s[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) s[t] = 0.0;
+    for (int g = threadIdx.x; g < groups; g += blockDim.x) {
+        const double* p = partials + ((uint64_t)g * V + v) * 16;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) s[t] += p[t];
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) red[threadIdx.x][t] = s[t];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int t = 0; t < 16; ++t) red[threadIdx.x][t] += red[threadIdx.x + w][t];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) dpose[v * 6 + threadIdx.x] = red[0][threadIdx.x];
+    else if (threadIdx.x < 15) dintr[v * 9 + threadIdx.x - 6] = red[0][threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+static inline Background make_bg(const float* bg, int C) {
+    Background b;
+    for (int c = 0; c < 16; ++c) b.v[c] = (bg && c < C) ? bg[c] : 0.0f;
+    return b;
+}
+
+static inline unsigned grid_for(int64_t items, int64_t per_group, int cap) {
+    int64_t g = (items + per_group - 1) / per_group;
+    g = (g + kXcds - 1) / kXcds * kXcds;
+    if (g < kXcds) g = kXcds;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+template <int C, typename S>
+static hipError_t forward_impl(const FwdArgs& a, hipStream_t st) {
+    const int cap = a.cus * 8 / kXcds * kXcds;
+    unsigned gp = grid_for(a.pixels, 256 * 4, a.cus * 8);
+    a.timer.mark(kKClear, 0, st);
+    k_clear<<<gp, 256, 0, st>>>(a.keys, a.counts, a.sums, a.pixels, a.pixels * C);
+    a.timer.mark(kKClear, 1, st);
+    unsigned g = grid_for(a.n, kBlock, cap);
+    if (a.n > 0) {
+        a.timer.mark(kKDepth, 0, st);
+        k_depth<<<g, kBlock, 0, st>>>(a.x, a.y, a.z, a.orig, a.n, a.views, a.V, a.L, a.keys);
+        a.timer.mark(kKDepth, 1, st);
+        a.timer.mark(kKAccum, 0, st);
+        k_accum<C, S><<<g, kBlock, 0, st>>>(a.x, a.y, a.z, a.feat, a.n, a.views, a.V, a.L, a.fa,
+                                             reinterpret_cast<const uint32_t*>(a.keys), a.sums, a.counts);
+        a.timer.mark(kKAccum, 1, st);
+    }
+    dim3 gn((unsigned)std::min<int64_t>((a.max_layer_pixels + 255) / 256, 1024), (unsigned)(a.V * a.L));
+    a.timer.mark(kKNormalize, 0, st);
+    k_normalize<C><<<gn, 256, 0, st>>>(a.views, a.L, a.sums, a.counts, a.images, make_bg(a.background, C));
+    a.timer.mark(kKNormalize, 1, st);
+    return hipGetLastError();
+}
+
+template <int C, typename S>
+static hipError_t backward_impl(const BwdArgs& a, hipStream_t st) {
+    constexpr int PPL = C <= 4 ? 4 : 2;
+    dim3 gn((unsigned)std::min<int64_t>((a.max_layer_pixels + 255) / 256, 1024), (unsigned)(a.V * a.L));
+    a.timer.mark(kKPack, 0, st);
+    k_pack<C><<<gn, 256, 0, st>>>(a.views, a.L, a.keys, a.counts, a.images, a.grad, a.pack,
+                                 make_bg(a.background, C));
+    a.timer.mark(kKPack, 1, st);
+    unsigned g = (unsigned)a.groups;
+    size_t lds = (size_t)4 * a.V * 16 * sizeof(double);
+    a.timer.mark(kKBackward, 0, st);
+    k_backward<C, S, PPL><<<g, kBlock, lds, st>>>(a.x, a.y, a.z, a.feat, a.n, a.views, a.V, a.L, a.fa,
+                                                  a.flags, a.pack, a.dfeat, a.dpos, a.partials);
+    a.timer.mark(kKBackward, 1, st);
+    a.timer.mark(kKReduce, 0, st);
+    k_reduce<<<a.V, 256, 0, st>>>(a.partials, (int)g, a.V, a.dpose, a.dintr);
+    a.timer.mark(kKReduce, 1, st);
+    return hipGetLastError();
+}
+
+int backward_points_per_group(int C) { return kBlock * (C <= 4 ? 4 : 2); }
+
+#define ADOP_DISPATCH_C(FN, S, ARGS, ST)            \
+    switch (ARGS.C) {                               \
+        case 1: return FN<1, S>(ARGS, ST);          \
+        case 2: return FN<2, S>(ARGS, ST);          \
+        case 3: return FN<3, S>(ARGS, ST);          \
+        case 4: return FN<4, S>(ARGS, ST);          \
+        case 5: return FN<5, S>(ARGS, ST);          \
+        case 6: return FN<6, S>(ARGS, ST);          \
+        case 7: return FN<7, S>(ARGS, ST);          \
+        case 8: return FN<8, S>(ARGS, ST);          \
+        case 9: return FN<9, S>(ARGS, ST);          \
+        case 10: return FN<10, S>(ARGS, ST);        \
+        case 11: return FN<11, S>(ARGS, ST);        \
+        case 12: return FN<12, S>(ARGS, ST);        \
+        case 13: return FN<13, S>(ARGS, ST);        \
+        case 14: return FN<14, S>(ARGS, ST);        \
+        case 15: return FN<15, S>(ARGS, ST);        \
+        case 16: return FN<16, S>(ARGS, ST);        \
+        default: return hipErrorInvalidValue;       \
+    }
+
+hipError_t launch_forward(const FwdArgs& a, hipStream_t st) {
+    switch (a.dtype) {
+        case 0: ADOP_DISPATCH_C(forward_impl, F32, a, st)
+        case 1: ADOP_DISPATCH_C(forward_impl, BF16, a, st)
+        case 2: ADOP_DISPATCH_C(forward_impl, F16, a, st)
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_backward(const BwdArgs& a, hipStream_t st) {
+    switch (a.dtype) {
+        case 0: ADOP_DISPATCH_C(backward_impl, F32, a, st)
+        case 1: ADOP_DISPATCH_C(backward_impl, BF16, a, st)
+        case 2: ADOP_DISPATCH_C(backward_impl, F16, a, st)
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace adop

@@ -1,0 +1,217 @@
+"""GPU parity: the HIP path through the C ABI vs the CPU oracle, element by
+element, on seeded inputs.  Keys, counts and coverage are bit-exact; images
+within 1e-5 relative; gradients within the per-quantity bounds (dfeat 1e-5*S,
+dpos 1e-4*S, pose/intrinsics 1e-5*S, S = the oracle's sum of |terms|)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2110_06635_amd import synth
+from tests.gpu_parity_lib import run_case, say, to_device_scene, gpu_forward, frame_numpy
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G(oracle):
+    import torch
+    from paper_2110_06635_amd import adop
+    assert torch.cuda.is_available()
+    ctx = adop.Context(0)
+    return adop, ctx, oracle
+
+
+def small_scene(seed, n, w=160, h=120, L=3, c=4, dist=True, box=2.0, depth=6.0):
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(-box, box, (n, 3)).astype(np.float32)
+    feat = rng.random((n, c)).astype(np.float32)
+    k = dict(k1=-0.08, k2=0.01, k3=0.001, p1=5e-4, p2=-5e-4) if dist else {}
+    cam = synth.Camera(w, h, 0.9 * w, 0.9 * w, w / 2.0 - 0.3, h / 2.0 + 0.2,
+                       r2_max=synth.r2_max_for(k.get("k1", 0), k.get("k2", 0), k.get("k3", 0),
+                                               k.get("p1", 0), k.get("p2", 0)),
+                       t=np.array([0.1, -0.05, depth]), R=synth.rodrigues([0.03, -0.02, 0.01]), **k)
+    return synth.Scene(pos, feat, [cam], layers=L, name=f"small-{seed}")
+
+
+def test_small_forward_backward(G):
+    A, ctx, O = G
+    s = small_scene(1, 20000)
+    say("small 20k 160x120 L3 f32 prepared")
+    rep = run_case(A, ctx, O, s)
+    print(rep)
+
+
+def test_small_identity_order(G):
+    A, ctx, O = G
+    s = small_scene(2, 7777)
+    say("small 7777 identity order")
+    run_case(A, ctx, O, s, prepare=False)
+
+
+def test_ragged_and_tiny(G):
+    A, ctx, O = G
+    for n in (1, 63, 65, 257, 1037, 4099):
+        s = small_scene(10 + n, n, w=64, h=48, L=3)
+        say(f"ragged n={n}")
+        run_case(A, ctx, O, s)
+
+
+def test_empty_scene(G):
+    import torch
+    A, ctx, O = G
+    s = small_scene(3, 0)
+    s.background = np.array([0.25, -1.0, 2.0, 0.5], np.float32)
+    say("empty scene")
+    run_case(A, ctx, O, s, prepare=False)
+
+
+def test_all_behind_camera(G):
+    A, ctx, O = G
+    s = small_scene(4, 3000, depth=-10.0)
+    say("all behind camera")
+    run_case(A, ctx, O, s)
+
+
+def test_single_pixel_contention(G):
+    """Every point lands in one pixel at every layer: the wave-uniform
+    reduction path, exact depth ties (duplicated points) and a large count."""
+    A, ctx, O = G
+    rng = np.random.default_rng(5)
+    n = 50000
+    cam = synth.Camera(64, 64, 50.0, 50.0, 32.0, 32.0, t=np.array([0.0, 0.0, 5.0]))
+    pos = np.zeros((n, 3), np.float32)
+    pos[:, 2] = rng.choice(np.array([0.0, 0.01, 0.02, 0.03, 1.0], np.float32), n)
+    pos[:, 0] = rng.uniform(-1e-3, 1e-3, n).astype(np.float32)
+    feat = rng.random((n, 4)).astype(np.float32)
+    s = synth.Scene(pos, feat, [cam], layers=4, name="one-pixel")
+    say("single pixel contention 50k")
+    run_case(A, ctx, O, s)
+
+
+def test_half_integer_ties(G):
+    """Points projected exactly onto pixel borders (round half to even) and
+    at exactly equal depths."""
+    A, ctx, O = G
+    rng = np.random.default_rng(6)
+    n = 6000
+    cam = synth.Camera(64, 48, 1.0, 1.0, 0.0, 0.0)
+    u = rng.integers(-2, 130, n) * 0.5
+    v = rng.integers(-2, 98, n) * 0.5
+    z = rng.choice(np.array([1.0, 2.0, 4.0]), n)
+    pos = np.stack([u * z, v * z, z], axis=1).astype(np.float32)
+    feat = rng.random((n, 2)).astype(np.float32)
+    s = synth.Scene(pos, feat, [cam], layers=3, name="ties")
+    say("half-integer ties")
+    run_case(A, ctx, O, s)
+
+
+@pytest.mark.parametrize("c", [1, 3, 8, 16])
+def test_channels(G, c):
+    A, ctx, O = G
+    s = small_scene(20 + c, 9000, c=c)
+    say(f"channels {c}")
+    run_case(A, ctx, O, s)
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_precision_same_rounded_inputs(G, dtype):
+    """BF16/FP16 storage, FP32 accumulation: equal to the oracle run on the
+    same rounded (then exactly widened) features."""
+    A, ctx, O = G
+    s = small_scene(30, 30000, c=4)
+    say(f"precision {dtype}")
+    run_case(A, ctx, O, s, dtype=dtype)
+
+
+@pytest.mark.parametrize("dtype,tol", [("bf16", 1e-2), ("f16", 1e-3)])
+def test_precision_vs_fp32_oracle(G, dtype, tol):
+    A, ctx, O = G
+    s = small_scene(31, 30000, c=4)
+    say(f"precision {dtype} vs fp32 oracle")
+    scene, _ = to_device_scene(A, ctx, s, dtype)
+    fr = gpu_forward(A, ctx, scene, s)
+    ref = O.forward(s.pos, s.feat, s.cams, s.layers, want64=True)
+    keys, counts, images = frame_numpy(fr)
+    assert np.array_equal(keys, ref["keys"]) and np.array_equal(counts, ref["counts"])
+    r64 = ref["images64"]
+    err = np.abs(images.astype(np.float64) - r64)
+    # relative bound, with an absolute floor for means of a few near-zero
+    # features (subnormal in FP16)
+    assert np.all(err <= tol * np.abs(r64) + 1e-4), float(np.max(err / (np.abs(r64) + 1e-4)))
+
+
+def test_alpha_zero_background_spatial_all(G):
+    A, ctx, O = G
+    s = small_scene(40, 15000)
+    s.background = np.array([0.1, 0.2, -0.3, 0.4], np.float32)
+    say("alpha 0, background, SPATIAL_ALL")
+    run_case(A, ctx, O, s, alpha=0.0, flags=1)
+    say("alpha 0.05")
+    run_case(A, ctx, O, s, alpha=0.05)
+
+
+def test_many_layers_and_one_layer(G):
+    A, ctx, O = G
+    s = small_scene(41, 12000, w=256, h=128, L=8)
+    say("L=8")
+    run_case(A, ctx, O, s)
+    s1 = small_scene(42, 12000, w=100, h=70, L=1)
+    say("L=1")
+    run_case(A, ctx, O, s1)
+
+
+def test_multiview_mixed_sizes(G):
+    A, ctx, O = G
+    rng = np.random.default_rng(43)
+    n = 20000
+    pos = rng.uniform(-1.5, 1.5, (n, 3)).astype(np.float32)
+    feat = rng.random((n, 3)).astype(np.float32)
+    cams = synth.orbit_cameras(3, 6.0, 44, width=96, height=64, f=60.0)
+    cams[1] = synth.orbit_cameras(3, 6.0, 45, width=160, height=90, f=100.0)[1]
+    cams[2] = synth.orbit_cameras(3, 5.0, 46, width=48, height=40, f=30.0)[2]
+    s = synth.Scene(pos, feat, cams, layers=3, name="multiview")
+    say("multiview mixed sizes")
+    run_case(A, ctx, O, s)
+
+
+def test_deterministic_reruns(G):
+    """Keys and counts are bit-identical over reruns (atomic-race canary).
+    The blended images are FP32 atomic sums, so they may differ in the last
+    bits between runs; for one given frame the backward pass is bit-identical
+    (fixed FP64 reduction order, no atomics)."""
+    import torch
+    A, ctx, O = G
+    s = synth.config2(n_planes=20, per_plane=20000)
+    say("determinism config-2 shape 400k")
+    scene, _ = to_device_scene(A, ctx, s)
+    fr1 = gpu_forward(A, ctx, scene, s)
+    k1, c1, i1 = frame_numpy(fr1)
+    G_ = torch.from_numpy(synth.upstream_grad(fr1.pixels * 4, 3)).cuda()
+    b1 = [t.cpu().numpy() for t in A.render_backward(ctx, scene, fr1, G_)]
+    b2 = [t.cpu().numpy() for t in A.render_backward(ctx, scene, fr1, G_)]
+    for a, b in zip(b1, b2):
+        assert np.array_equal(a, b)
+    fr2 = A.Frame(s.cams, s.layers, 4, scene.x.device)
+    A.render_forward(ctx, scene, s.cams, s.layers, frame=fr2, background=s.bg())
+    torch.cuda.synchronize()
+    k2, c2, i2 = frame_numpy(fr2)
+    assert np.array_equal(k1, k2) and np.array_equal(c1, c2)
+    np.testing.assert_allclose(i1, i2, rtol=2e-6, atol=1e-7)
+
+
+def test_config1_forward(G):
+    A, ctx, O = G
+    s = synth.config1()
+    say("config 1 (100k uniform box, 640x480, L4) forward")
+    rep = run_case(A, ctx, O, s, backward=False)
+    print(rep)
+
+
+def test_config2_forward_backward(G):
+    """Full config 2: 10M points on 200 planes, 1920x1080 with distortion, L=5."""
+    A, ctx, O = G
+    s = synth.config2()
+    say("config 2 (10M planes, 1080p, L5) forward+backward")
+    rep = run_case(A, ctx, O, s)
+    print(rep)
