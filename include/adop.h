@@ -147,10 +147,13 @@ size_t adop_feature_bytes(int64_t n, int32_t channels, adop_dtype dtype);
 
 /* ------------------------------------------------------- scene upload */
 /* Reorder a point cloud for rendering (Sec. 3.1, "Implementation Details":
- * the blocked Morton shuffle).  Points are sorted by a 63-bit Morton code
- * over their bounding box, cut into 8 contiguous segments (one per XCD), and
- * blocks of `block` points (a multiple of 256; 0 = 1024) are shuffled inside
- * each segment with a permutation drawn from `seed`.
+ * Morton order of the cloud).  Points are sorted by a 63-bit Morton code over
+ * their bounding box (21 bits per axis; non-finite points last).  The render
+ * kernels give every workgroup a contiguous range of this order, i.e. a
+ * compact region of space.  With block > 0 (a multiple of 256) the order is
+ * additionally cut into 8 segments and blocks of `block` points are shuffled
+ * inside each segment with a permutation drawn from `seed` (the blocked
+ * Morton shuffle); block == 0 keeps the plain Morton order (default).
  *   pos       device [n][3] FP32, caller's order
  *   feat      device [n][C] of dtype, caller's order
  *   x,y,z     device [n] FP32 outputs (SoA positions)

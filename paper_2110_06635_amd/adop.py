@@ -226,9 +226,9 @@ class Scene:
 
     @staticmethod
     def prepare(ctx: Context, pos: torch.Tensor, feat: torch.Tensor, dtype: int = F32,
-                block: int = 1024, seed: int = 1, stream=None) -> "Scene":
-        """Blocked Morton shuffle of a device point cloud (pos [n,3] FP32,
-        feat [n,C] in the storage dtype)."""
+                block: int = 0, seed: int = 1, stream=None) -> "Scene":
+        """Morton order (and optional block shuffle, block > 0) of a device
+        point cloud (pos [n,3] FP32, feat [n,C] in the storage dtype)."""
         dev = pos.device
         n = int(pos.shape[0])
         C = int(feat.shape[1])

@@ -396,8 +396,7 @@ adop_status adop_scene_prepare(adop_context* ctx, const float* pos, const void* 
     if (n < 0 || n > 0x7fffffffLL) return fail(ctx, ADOP_E_INVALID, "n=%lld outside [0, 2^31-1]", (long long)n);
     if (channels < 1 || channels > ADOP_MAX_CHANNELS) return fail(ctx, ADOP_E_UNSUPPORTED, "channels=%d", channels);
     if (dtype < ADOP_F32 || dtype > ADOP_F16) return fail(ctx, ADOP_E_UNSUPPORTED, "dtype %d", dtype);
-    if (block == 0) block = 1024;
-    if (block < 256 || block % 256 != 0) return fail(ctx, ADOP_E_INVALID, "block=%d must be a positive multiple of 256", block);
+    if (block < 0 || block % 256 != 0) return fail(ctx, ADOP_E_INVALID, "block=%d must be 0 or a positive multiple of 256", block);
     if (n > 0 && (!pos || !feat || !x || !y || !z || !feat_out || !orig_index))
         return fail(ctx, ADOP_E_INVALID, "NULL pointer");
     if (n > 0 && ((uintptr_t)feat_out & 15) != 0) return fail(ctx, ADOP_E_INVALID, "feat_out must be 16-byte aligned");
@@ -443,12 +442,8 @@ adop_status adop_render_backward(adop_context* ctx, const adop_scene* scene, con
     a.C = scene->channels;
     a.V = V;
     a.L = params->layers;
-    int ppg = adop::backward_points_per_group(a.C);
-    int64_t g = (scene->n + ppg - 1) / ppg;
-    g = (g + 7) / 8 * 8;
-    g = std::max<int64_t>(g, 8);
-    g = std::min<int64_t>(g, bwd_group_cap(ctx->cus));
-    a.groups = (int)g;
+    a.cus = ctx->cus;
+    a.groups = bwd_group_cap(ctx->cus);   // upper bound of the backward grid (partials buffer)
     a.flags = params->flags;
     a.n = scene->n;
     a.pixels = total;

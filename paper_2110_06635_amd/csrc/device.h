@@ -241,36 +241,55 @@ template <int C> struct PackLayout {
     static constexpr int gdot = C, minz = C + 1, count = C + 2;
 };
 
-// Chunk mapping of point kernels: workgroup b runs on XCD b % 8; the points
-// are split into 8 contiguous segments (segment boundaries rounded down to
-// `seg_align` points) and the workgroups of XCD x stride over the chunks of
-// segment x, so that each XCD renders one region of the Morton-ordered cloud
-// and its L2 keeps that region's pixels.
-struct ChunkMap {
-    int64_t n;
-    int64_t seg_lo, seg_hi;   // this workgroup's segment, in points
-    int64_t first, step;      // first chunk start and stride, in points
+// Range mapping of the point kernels: the grid is persistent (a multiple of
+// 8 workgroups) and workgroup b, which runs on XCD b % 8, owns one contiguous
+// range of chunks.  Ranges are numbered so that the workgroups of XCD x own
+// the x-th eighth of the (Morton-ordered) points: every workgroup renders a
+// spatially compact part of the cloud and every XCD's L2 serves one region.
+struct RangeMap {
+    int64_t c0, c1;   // chunk indices [c0, c1)
 };
 
-__device__ __forceinline__ int64_t segment_bound(int64_t n, int x, int64_t align) {
-    if (x >= kXcds) return n;
-    int64_t b = (n * x) / kXcds;
-    return b / align * align;
+__device__ __forceinline__ RangeMap range_map(int64_t n, int64_t chunk) {
+    RangeMap m;
+    const int64_t nc = (n + chunk - 1) / chunk;
+    const int G = (int)gridDim.x;
+    const int b = (int)blockIdx.x;
+    const int64_t r = (int64_t)(b % kXcds) * (G / kXcds) + b / kXcds;
+    m.c0 = nc * r / G;
+    m.c1 = nc * (r + 1) / G;
+    return m;
 }
 
-__device__ __forceinline__ ChunkMap chunk_map(int64_t n, int64_t chunk, int64_t align) {
-    ChunkMap m;
-    m.n = n;
-    int g = (int)gridDim.x;
-    int b = (int)blockIdx.x;
-    int x = b % kXcds;
-    int per = g / kXcds;            // grid is a multiple of 8
-    int k = b / kXcds;
-    m.seg_lo = segment_bound(n, x, align);
-    m.seg_hi = segment_bound(n, x + 1, align);
-    m.first = m.seg_lo + (int64_t)k * chunk;
-    m.step = (int64_t)per * chunk;
-    return m;
+// ----------------------------------------------------------------------------
+// workgroup-private open-addressing tables in LDS (pixel -> partial result)
+// ----------------------------------------------------------------------------
+constexpr uint32_t kEmptySlot = 0xffffffffu;
+constexpr int kProbes = 8;
+
+template <int BITS>
+__device__ __forceinline__ uint32_t hash_slot(uint32_t pix) {
+    return (pix * 2654435761u) >> (32 - BITS);
+}
+
+// Find or claim the slot of `pix`; -1 (and *full = 1) when kProbes slots
+// after its home slot are taken by other pixels.
+template <int BITS>
+__device__ __forceinline__ int table_slot(uint32_t* tkey, uint32_t pix, int* full) {
+    constexpr uint32_t mask = (1u << BITS) - 1;
+    uint32_t h = hash_slot<BITS>(pix);
+#pragma unroll 1
+    for (int p = 0; p < kProbes; ++p) {
+        uint32_t k = __hip_atomic_load(&tkey[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (k == pix) return (int)h;
+        if (k == kEmptySlot) {
+            uint32_t old = atomicCAS(&tkey[h], kEmptySlot, pix);
+            if (old == kEmptySlot || old == pix) return (int)h;
+        }
+        h = (h + 1) & mask;
+    }
+    *full = 1;
+    return -1;
 }
 
 }  // namespace adop

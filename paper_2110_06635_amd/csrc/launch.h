@@ -42,7 +42,7 @@ struct FwdArgs {
 };
 
 struct BwdArgs {
-    int dtype, C, V, L, groups;
+    int dtype, C, V, L, cus, groups;   // groups: largest backward grid the partials buffer holds
     uint32_t flags;
     int64_t n, pixels, max_layer_pixels;
     float fa;

@@ -44,20 +44,65 @@ __global__ void __launch_bounds__(256) k_clear(uint64_t* __restrict__ keys, int3
         sums[i] = 0.f;
 }
 
-__device__ __forceinline__ void depth_update(bool in, uint32_t pix, uint64_t key, uint64_t* __restrict__ keys) {
+// ---- depth pass -----------------------------------------------------------
+// Per-workgroup LDS table pixel -> minimum key.  A wave whose active lanes all
+// hit one pixel takes the wave minimum (DPP) and updates once; otherwise each
+// lane updates.  Updates read the current value first and issue the atomic
+// minimum only when they would lower it (keys only decrease, so a stale read
+// can only let an unnecessary atomic through).
+constexpr int kDepthBits = 11;
+constexpr int kDepthH = 1 << kDepthBits;
+
+struct DepthTable {
+    uint32_t key[kDepthH];
+    uint64_t val[kDepthH];
+    int full;
+};
+
+__device__ __forceinline__ void global_min(uint64_t* __restrict__ gkeys, uint32_t pix, uint64_t k) {
+    uint64_t cur = load_relaxed_u64(gkeys + pix);
+    if (k < cur) atomic_min_u64(gkeys + pix, k);
+}
+
+__device__ __forceinline__ void table_min(DepthTable& t, uint64_t* __restrict__ gkeys, uint32_t pix, uint64_t k) {
+    int slot = table_slot<kDepthBits>(t.key, pix, &t.full);
+    if (slot < 0) {
+        global_min(gkeys, pix, k);
+        return;
+    }
+    uint64_t cur = __hip_atomic_load(&t.val[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (k < cur) __hip_atomic_fetch_min(&t.val[slot], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void depth_update(bool in, uint32_t pix, uint64_t key, DepthTable& t,
+                                             uint64_t* __restrict__ gkeys) {
     uint64_t m = ballot(in);
     if (m == 0) return;
     int leader = __builtin_ctzll(m);
     uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pix, leader);
     if (ballot(in && pix != p0) == 0) {
         uint64_t k = wave_min_u64(in ? key : ~0ull);
-        if (lane_id() == leader) {
-            uint64_t cur = load_relaxed_u64(keys + p0);
-            if (k < cur) atomic_min_u64(keys + p0, k);
-        }
+        if (lane_id() == leader) table_min(t, gkeys, p0, k);
     } else if (in) {
-        uint64_t cur = load_relaxed_u64(keys + pix);
-        if (key < cur) atomic_min_u64(keys + pix, key);
+        table_min(t, gkeys, pix, key);
+    }
+}
+
+__device__ __forceinline__ void depth_table_clear(DepthTable& t) {
+    for (int j = threadIdx.x; j < kDepthH; j += blockDim.x) {
+        t.key[j] = kEmptySlot;
+        t.val[j] = ~0ull;
+    }
+}
+
+__device__ __forceinline__ void depth_table_flush(DepthTable& t, uint64_t* __restrict__ gkeys) {
+    for (int j = threadIdx.x; j < kDepthH; j += blockDim.x) {
+        uint32_t k = t.key[j];
+        if (k != kEmptySlot) {
+            global_min(gkeys, k, t.val[j]);
+            t.key[j] = kEmptySlot;
+            t.val[j] = ~0ull;
+        }
     }
 }
 
@@ -65,10 +110,14 @@ __global__ void __launch_bounds__(256) k_depth(const float* __restrict__ xs, con
                                                const float* __restrict__ zs, const int32_t* __restrict__ orig,
                                                int64_t n, const ViewRec* __restrict__ views, int V, int L,
                                                uint64_t* __restrict__ keys) {
-    ChunkMap m = chunk_map(n, kBlock, kSegAlign);
-    for (int64_t base = m.first; base < m.seg_hi; base += m.step) {
-        int64_t i = base + threadIdx.x;
-        bool live = i < m.seg_hi;
+    __shared__ DepthTable t;
+    depth_table_clear(t);
+    if (threadIdx.x == 0) t.full = 0;
+    __syncthreads();
+    RangeMap m = range_map(n, kBlock);
+    for (int64_t c = m.c0; c < m.c1; ++c) {
+        int64_t i = c * kBlock + threadIdx.x;
+        bool live = i < n;
         float x = 0.f, y = 0.f, z = 0.f;
         uint32_t oi = 0;
         if (live) {
@@ -78,42 +127,110 @@ __global__ void __launch_bounds__(256) k_depth(const float* __restrict__ xs, con
             oi = (uint32_t)orig[i];
         }
         for (int v = 0; v < V; ++v) {
-            const ViewRec& c = views[v];
-            Proj p = project(c, x, y, z);
+            const ViewRec& cam = views[v];
+            Proj p = project(cam, x, y, z);
             bool ok = live && p.ok;
             uint64_t key = ((uint64_t)__float_as_uint(p.Z) << 32) | oi;
             for (int l = 0; l < L; ++l) {
                 int px = 0, py = 0;
                 uint32_t pix = 0;
-                bool in = ok && layer_pixel(c, l, p.u0, p.v0, px, py, pix);
-                depth_update(in, pix, key, keys);
+                bool in = ok && layer_pixel(cam, l, p.u0, p.v0, px, py, pix);
+                depth_update(in, pix, key, t, keys);
             }
         }
+        __syncthreads();
+        if (t.full) {
+            depth_table_flush(t, keys);
+            __syncthreads();
+            if (threadIdx.x == 0) t.full = 0;
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    depth_table_flush(t, keys);
+}
+
+// ---- accumulation pass ----------------------------------------------------
+// Per-workgroup LDS table pixel -> (feature sums, count).  Inside a wave the
+// passing lanes are grouped by pixel (leader loop: the first remaining lane's
+// pixel, the ballot of lanes sharing it, DPP sums) so that one lane adds a
+// group's total; lanes left when the groups become small add individually.
+constexpr int kMaxGroups = 6;
+constexpr int kMinGroup = 3;
+
+template <int C> struct AccTable {
+    static constexpr int bits = C <= 4 ? 10 : (C <= 8 ? 9 : 8);
+    static constexpr int H = 1 << bits;
+    uint32_t key[H];
+    float sum[C][H];
+    int32_t cnt[H];
+    int full;
+};
+
+template <int C>
+__device__ __forceinline__ void table_add(AccTable<C>& t, float* __restrict__ sums, int32_t* __restrict__ counts,
+                                          uint32_t pix, const float (&s)[C], int32_t k) {
+    int slot = table_slot<AccTable<C>::bits>(t.key, pix, &t.full);
+    if (slot < 0) {
+        float* dst = sums + (uint64_t)pix * C;
+#pragma unroll
+        for (int c = 0; c < C; ++c) atomic_add_f32(dst + c, s[c]);
+        atomic_add_i32(counts + pix, k);
+        return;
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        __hip_atomic_fetch_add(&t.sum[c][slot], s[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(&t.cnt[slot], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <int C>
+__device__ __forceinline__ void accum_update(bool pass, uint32_t pix, const float (&f)[C], AccTable<C>& t,
+                                             float* __restrict__ sums, int32_t* __restrict__ counts) {
+    uint64_t rem = ballot(pass);
+    const int lane = lane_id();
+#pragma unroll 1
+    for (int it = 0; it < kMaxGroups && rem != 0; ++it) {
+        int leader = __builtin_ctzll(rem);
+        uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pix, leader);
+        uint64_t mm = ballot(pass && pix == p0);
+        int k = __builtin_popcountll(mm);
+        if (k < kMinGroup) break;
+        bool mine = (mm >> lane) & 1;
+        float s[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) s[c] = wave_sum(mine ? f[c] : 0.0f);
+        if (lane == leader) table_add<C>(t, sums, counts, p0, s, k);
+        rem &= ~mm;
+    }
+    if ((rem >> lane) & 1) table_add<C>(t, sums, counts, pix, f, 1);
+}
+
+template <int C>
+__device__ __forceinline__ void acc_table_clear(AccTable<C>& t) {
+    for (int j = threadIdx.x; j < AccTable<C>::H; j += blockDim.x) {
+        t.key[j] = kEmptySlot;
+#pragma unroll
+        for (int c = 0; c < C; ++c) t.sum[c][j] = 0.f;
+        t.cnt[j] = 0;
     }
 }
 
 template <int C>
-__device__ __forceinline__ void accum_update(bool pass, uint32_t pix, const float (&f)[C],
-                                             float* __restrict__ sums, int32_t* __restrict__ counts) {
-    uint64_t m = ballot(pass);
-    if (m == 0) return;
-    int leader = __builtin_ctzll(m);
-    uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pix, leader);
-    if (ballot(pass && pix != p0) == 0) {
-        float s[C];
+__device__ __forceinline__ void acc_table_flush(AccTable<C>& t, float* __restrict__ sums, int32_t* __restrict__ counts) {
+    for (int j = threadIdx.x; j < AccTable<C>::H; j += blockDim.x) {
+        uint32_t k = t.key[j];
+        if (k != kEmptySlot) {
+            float* dst = sums + (uint64_t)k * C;
 #pragma unroll
-        for (int c = 0; c < C; ++c) s[c] = wave_sum(pass ? f[c] : 0.0f);
-        if (lane_id() == leader) {
-            float* dst = sums + (uint64_t)p0 * C;
-#pragma unroll
-            for (int c = 0; c < C; ++c) atomic_add_f32(dst + c, s[c]);
-            atomic_add_i32(counts + p0, (int32_t)__builtin_popcountll(m));
+            for (int c = 0; c < C; ++c) {
+                atomic_add_f32(dst + c, t.sum[c][j]);
+                t.sum[c][j] = 0.f;
+            }
+            atomic_add_i32(counts + k, t.cnt[j]);
+            t.cnt[j] = 0;
+            t.key[j] = kEmptySlot;
         }
-    } else if (pass) {
-        float* dst = sums + (uint64_t)pix * C;
-#pragma unroll
-        for (int c = 0; c < C; ++c) atomic_add_f32(dst + c, f[c]);
-        atomic_add_i32(counts + pix, 1);
     }
 }
 
@@ -123,14 +240,18 @@ __global__ void __launch_bounds__(256) k_accum(const float* __restrict__ xs, con
                                                int64_t n, const ViewRec* __restrict__ views, int V, int L,
                                                float fa, const uint32_t* __restrict__ keys32,
                                                float* __restrict__ sums, int32_t* __restrict__ counts) {
-    ChunkMap m = chunk_map(n, kBlock, kSegAlign);
-    for (int64_t base = m.first; base < m.seg_hi; base += m.step) {
-        int64_t i = base + threadIdx.x;
-        bool live = i < m.seg_hi;
+    __shared__ AccTable<C> t;
+    acc_table_clear<C>(t);
+    if (threadIdx.x == 0) t.full = 0;
+    __syncthreads();
+    RangeMap m = range_map(n, kBlock);
+    for (int64_t c = m.c0; c < m.c1; ++c) {
+        int64_t i = c * kBlock + threadIdx.x;
+        bool live = i < n;
         float x = 0.f, y = 0.f, z = 0.f;
         float f[C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) f[c] = 0.f;
+        for (int ch = 0; ch < C; ++ch) f[ch] = 0.f;
         if (live) {
             x = xs[i];
             y = ys[i];
@@ -138,22 +259,31 @@ __global__ void __launch_bounds__(256) k_accum(const float* __restrict__ xs, con
             load_feat<C, S>(feat, i, f);
         }
         for (int v = 0; v < V; ++v) {
-            const ViewRec& c = views[v];
-            Proj p = project(c, x, y, z);
+            const ViewRec& cam = views[v];
+            Proj p = project(cam, x, y, z);
             bool ok = live && p.ok;
             for (int l = 0; l < L; ++l) {
                 int px = 0, py = 0;
                 uint32_t pix = 0;
-                bool in = ok && layer_pixel(c, l, p.u0, p.v0, px, py, pix);
+                bool in = ok && layer_pixel(cam, l, p.u0, p.v0, px, py, pix);
                 bool pass = false;
                 if (in) {
                     float minz = __uint_as_float(keys32[2 * (uint64_t)pix + 1]);
                     pass = p.Z <= __fmul_rn(minz, fa);
                 }
-                accum_update<C>(pass, pix, f, sums, counts);
+                accum_update<C>(pass, pix, f, t, sums, counts);
             }
         }
+        __syncthreads();
+        if (t.full) {
+            acc_table_flush<C>(t, sums, counts);
+            __syncthreads();
+            if (threadIdx.x == 0) t.full = 0;
+            __syncthreads();
+        }
     }
+    __syncthreads();
+    acc_table_flush<C>(t, sums, counts);
 }
 
 struct Background {
@@ -280,16 +410,16 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
     __syncthreads();
     const bool spatial_all = (flags & 1u) != 0;
 
-    ChunkMap m = chunk_map(n, (int64_t)kBlock * PPL, kSegAlign);
-    for (int64_t base = m.first; base < m.seg_hi; base += m.step) {
-        const int64_t wbase = base + (int64_t)wave * kWave * PPL;
+    RangeMap m = range_map(n, (int64_t)kBlock * PPL);
+    for (int64_t c = m.c0; c < m.c1; ++c) {
+        const int64_t wbase = c * kBlock * PPL + (int64_t)wave * kWave * PPL;
         float px_[PPL], py_[PPL], pz_[PPL];
         float tau[PPL][C], dt[PPL][C], dp[PPL][3];
         bool live[PPL];
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
             int64_t i = wbase + (int64_t)k * kWave + lane;
-            live[k] = i < m.seg_hi;
+            live[k] = i < n;
             px_[k] = py_[k] = pz_[k] = 0.f;
 #pragma unroll
             for (int c = 0; c < C; ++c) { tau[k][c] = 0.f; dt[k][c] = 0.f; }
@@ -431,21 +561,44 @@ static inline unsigned grid_for(int64_t items, int64_t per_group, int cap) {
     return (unsigned)g;
 }
 
+// Resident workgroups per CU of a kernel (persistent grids).
+template <typename K>
+static int resident(K kernel, size_t dyn_lds) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, dyn_lds) != hipSuccess || nb < 1) nb = 1;
+    return nb;
+}
+
+// Persistent grid: every CU full once, a multiple of 8 (one range per
+// workgroup, XCD-major), and no more workgroups than chunks.
+static inline unsigned persistent_grid(int64_t n, int64_t chunk, int cus, int per_cu, int cap) {
+    int64_t g = (int64_t)cus * per_cu;
+    g = g / kXcds * kXcds;
+    int64_t need = (n + chunk - 1) / chunk;
+    need = (need + kXcds - 1) / kXcds * kXcds;
+    g = std::min<int64_t>(g, need);
+    g = std::min<int64_t>(g, cap);
+    if (g < kXcds) g = kXcds;
+    return (unsigned)g;
+}
+
 template <int C, typename S>
 static hipError_t forward_impl(const FwdArgs& a, hipStream_t st) {
-    const int cap = a.cus * 8 / kXcds * kXcds;
+    static const int occ_depth = resident(k_depth, 0);
+    static const int occ_accum = resident(k_accum<C, S>, 0);
     unsigned gp = grid_for(a.pixels, 256 * 4, a.cus * 8);
     a.timer.mark(kKClear, 0, st);
     k_clear<<<gp, 256, 0, st>>>(a.keys, a.counts, a.sums, a.pixels, a.pixels * C);
     a.timer.mark(kKClear, 1, st);
-    unsigned g = grid_for(a.n, kBlock, cap);
     if (a.n > 0) {
+        unsigned gd = persistent_grid(a.n, kBlock, a.cus, occ_depth, 1 << 20);
         a.timer.mark(kKDepth, 0, st);
-        k_depth<<<g, kBlock, 0, st>>>(a.x, a.y, a.z, a.orig, a.n, a.views, a.V, a.L, a.keys);
+        k_depth<<<gd, kBlock, 0, st>>>(a.x, a.y, a.z, a.orig, a.n, a.views, a.V, a.L, a.keys);
         a.timer.mark(kKDepth, 1, st);
+        unsigned ga = persistent_grid(a.n, kBlock, a.cus, occ_accum, 1 << 20);
         a.timer.mark(kKAccum, 0, st);
-        k_accum<C, S><<<g, kBlock, 0, st>>>(a.x, a.y, a.z, a.feat, a.n, a.views, a.V, a.L, a.fa,
-                                             reinterpret_cast<const uint32_t*>(a.keys), a.sums, a.counts);
+        k_accum<C, S><<<ga, kBlock, 0, st>>>(a.x, a.y, a.z, a.feat, a.n, a.views, a.V, a.L, a.fa,
+                                              reinterpret_cast<const uint32_t*>(a.keys), a.sums, a.counts);
         a.timer.mark(kKAccum, 1, st);
     }
     dim3 gn((unsigned)std::min<int64_t>((a.max_layer_pixels + 255) / 256, 1024), (unsigned)(a.V * a.L));
@@ -458,13 +611,14 @@ static hipError_t forward_impl(const FwdArgs& a, hipStream_t st) {
 template <int C, typename S>
 static hipError_t backward_impl(const BwdArgs& a, hipStream_t st) {
     constexpr int PPL = C <= 4 ? 4 : 2;
+    size_t lds = (size_t)4 * a.V * 16 * sizeof(double);
     dim3 gn((unsigned)std::min<int64_t>((a.max_layer_pixels + 255) / 256, 1024), (unsigned)(a.V * a.L));
     a.timer.mark(kKPack, 0, st);
     k_pack<C><<<gn, 256, 0, st>>>(a.views, a.L, a.keys, a.counts, a.images, a.grad, a.pack,
                                  make_bg(a.background, C));
     a.timer.mark(kKPack, 1, st);
-    unsigned g = (unsigned)a.groups;
-    size_t lds = (size_t)4 * a.V * 16 * sizeof(double);
+    static const int occ = resident(k_backward<C, S, PPL>, (size_t)4 * kMaxViewsBwd * 16 * sizeof(double));
+    unsigned g = persistent_grid(a.n, (int64_t)kBlock * PPL, a.cus, occ, a.groups);
     a.timer.mark(kKBackward, 0, st);
     k_backward<C, S, PPL><<<g, kBlock, lds, st>>>(a.x, a.y, a.z, a.feat, a.n, a.views, a.V, a.L, a.fa,
                                                   a.flags, a.pack, a.dfeat, a.dpos, a.partials);

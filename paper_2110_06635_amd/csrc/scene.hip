@@ -4,9 +4,10 @@
 // 1. bounding box of the finite positions
 // 2. 63-bit Morton code (21 bits per axis) per point; non-finite points sort last
 // 3. radix sort of (code, index) pairs (rocPRIM)
-// 4. the sorted order is cut into 8 segments (the same boundaries the render
-//    kernels use to give each XCD one segment) and blocks of `block` points
-//    are shuffled inside each segment with a seeded permutation
+// 4. optionally, the sorted order is cut into 8 segments and blocks of
+//    `block` points are shuffled inside each segment with a seeded
+//    permutation (the shuffle of Schuetz et al.; the render kernels here give
+//    every workgroup a contiguous range instead, so the default is none)
 // 5. gather into SoA position planes, the feature array and orig_index.
 #include <rocprim/device/device_radix_sort.hpp>
 
@@ -180,8 +181,10 @@ hipError_t scene_prepare(const PrepArgs& a, hipStream_t st) {
     ADOP_CK(rocprim::radix_sort_pairs(tmp.p, tmp_bytes, (uint64_t*)codes.p, (uint64_t*)codes2.p,
                                       (int32_t*)idx.p, (int32_t*)idx2.p, (size_t)n, 0, 63, st));
 
-    // block permutation inside each segment (host)
-    const int block = a.block;
+    // block permutation inside each segment (host); block == 0 keeps the
+    // plain Morton order
+    const bool shuffle = a.block > 0;
+    const int block = shuffle ? a.block : 1024;
     std::vector<int64_t> seg(9), blk_base(9);
     for (int x = 0; x <= 8; ++x) seg[x] = host_segment_bound(n, x);
     int64_t nblocks = 0;
@@ -197,7 +200,7 @@ hipError_t scene_prepare(const PrepArgs& a, hipStream_t st) {
         if (nb == 0) continue;
         std::vector<int64_t> order(nb);
         for (int64_t k = 0; k < nb; ++k) order[k] = k;
-        for (int64_t k = nb - 1; k > 0; --k) {
+        for (int64_t k = nb - 1; shuffle && k > 0; --k) {
             int64_t j = (int64_t)(splitmix64(rs) % (uint64_t)(k + 1));
             std::swap(order[k], order[j]);
         }

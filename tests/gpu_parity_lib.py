@@ -15,7 +15,7 @@ def say(msg):
     sys.stdout.flush()
 
 
-def to_device_scene(A, ctx, s, dtype="f32", prepare=True, block=1024, seed=7):
+def to_device_scene(A, ctx, s, dtype="f32", prepare=True, block=0, seed=7):
     import torch
     raw, widened = synth.storage(s.feat, dtype)
     pos = torch.from_numpy(np.ascontiguousarray(s.pos)).cuda()
