@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--variants", default="bf16,f16", help="extra feature storage types to time")
     ap.add_argument("--cpu-sample", type=int, default=4_000_000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -103,6 +105,15 @@ def main():
     import torch
     from paper_2110_06635_amd import adop, synth
 
+    if args.copy_probe_mib > 0:
+        nb = args.copy_probe_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {nb} bytes read, {nb} bytes written")
+        del src, dst
     t0 = time.time()
     s = synth.config3(n=args.n)
     log(f"generated {s.name} in {time.time() - t0:.1f}s")

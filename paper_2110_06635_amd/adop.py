@@ -16,7 +16,9 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libadop.so")
+# ADOP_LIB selects another build of the same library (e.g. one compiled with
+# different tuning macros); the default is the in-tree libadop.so.
+LIB_PATH = os.environ.get("ADOP_LIB", os.path.join(HERE, "libadop.so"))
 
 OK, E_INVALID, E_UNSUPPORTED, E_WORKSPACE, E_DEVICE, E_STATE = range(6)
 F32, BF16, F16 = 0, 1, 2
@@ -301,6 +303,13 @@ def render_forward(ctx: Context, scene: Scene, cams, layers: int, alpha: float =
     C = scene.channels
     if frame is None:
         frame = Frame(cams, layers, C, scene.x.device)
+    else:
+        arr = cams if isinstance(cams, ct.Array) else make_cameras(cams)
+        if len(arr) != len(frame.cams) or frame.layers != layers or frame.channels != C or any(
+                (arr[v].width, arr[v].height) != (frame.cams[v].width, frame.cams[v].height)
+                for v in range(len(arr))):
+            raise ValueError("cameras, layers or channels do not match the given frame")
+        frame.cams = arr
     ws = workspace if workspace is not None else ctx.workspace(C, len(frame.cams), frame.pixels)
     p, keep = _params(layers, alpha, flags, background, C)
     sd = scene.desc()

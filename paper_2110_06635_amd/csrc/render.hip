@@ -155,11 +155,20 @@ __global__ void __launch_bounds__(256) k_depth(const float* __restrict__ xs, con
 // passing lanes are grouped by pixel (leader loop: the first remaining lane's
 // pixel, the ballot of lanes sharing it, DPP sums) so that one lane adds a
 // group's total; lanes left when the groups become small add individually.
-constexpr int kMaxGroups = 6;
-constexpr int kMinGroup = 3;
+#ifndef ADOP_MAX_GROUPS
+#define ADOP_MAX_GROUPS 6
+#endif
+#ifndef ADOP_MIN_GROUP
+#define ADOP_MIN_GROUP 3
+#endif
+#ifndef ADOP_ACC_BITS4
+#define ADOP_ACC_BITS4 10
+#endif
+constexpr int kMaxGroups = ADOP_MAX_GROUPS;
+constexpr int kMinGroup = ADOP_MIN_GROUP;
 
 template <int C> struct AccTable {
-    static constexpr int bits = C <= 4 ? 10 : (C <= 8 ? 9 : 8);
+    static constexpr int bits = C <= 4 ? ADOP_ACC_BITS4 : (C <= 8 ? ADOP_ACC_BITS4 - 1 : ADOP_ACC_BITS4 - 2);
     static constexpr int H = 1 << bits;
     uint32_t key[H];
     float sum[C][H];
@@ -363,19 +372,24 @@ __global__ void __launch_bounds__(256) k_pack(const ViewRec* __restrict__ views,
 // joins q's blend set -> (tau - I(q)) / (n+1).  With gdot = <G, I(q)> (or
 // <G, b>), every case is factor * (<G(q), tau> - gdot).
 template <int C>
-__device__ __forceinline__ float induced(const float* __restrict__ pack, uint64_t q, float Z, float fa,
-                                         const float (&tau)[C]) {
+__device__ __forceinline__ void load_rec(const float* __restrict__ pack, uint64_t q,
+                                         float (&rec)[PackLayout<C>::stride]) {
     using PL = PackLayout<C>;
-    const float* r = pack + q * PL::stride;
-    float rec[PL::stride];
+    const float4* r = reinterpret_cast<const float4*>(pack + q * PL::stride);
 #pragma unroll
     for (int k = 0; k < PL::stride / 4; ++k) {
-        float4 t4 = reinterpret_cast<const float4*>(r)[k];
+        float4 t4 = r[k];
         rec[4 * k] = t4.x;
         rec[4 * k + 1] = t4.y;
         rec[4 * k + 2] = t4.z;
         rec[4 * k + 3] = t4.w;
     }
+}
+
+template <int C>
+__device__ __forceinline__ float induced_rec(const float (&rec)[PackLayout<C>::stride], float Z, float fa,
+                                             const float (&tau)[C]) {
+    using PL = PackLayout<C>;
     int nq = __float_as_int(rec[PL::count]);
     float mq = rec[PL::minz];
     float dot = 0.f;
@@ -394,6 +408,48 @@ __device__ __forceinline__ float induced(const float* __restrict__ pack, uint64_
     }
     return factor * t;
 }
+
+template <int C>
+__device__ __forceinline__ float induced(const float* __restrict__ pack, uint64_t q, float Z, float fa,
+                                         const float (&tau)[C]) {
+    float rec[PackLayout<C>::stride];
+    load_rec<C>(pack, q, rec);
+    return induced_rec<C>(rec, Z, fa, tau);
+}
+
+// One point at one layer: feature gradient and the layer's dL/du, dL/dv.
+// `pix`, `qx`, `qy` may be wave-uniform (all lanes on one pixel), in which
+// case every record load is a scalar load.
+template <int C>
+__device__ __forceinline__ void point_layer(const float* __restrict__ pack, uint32_t pix, int qx, int qy, int lw,
+                                            int lh, float Z, float fa, bool spatial_all, const float (&tau)[C],
+                                            float (&dt)[C], float& du, float& dv) {
+    using PL = PackLayout<C>;
+    const float* r = pack + (uint64_t)pix * PL::stride;
+    float minz = r[PL::minz];
+    bool vis = Z <= __fmul_rn(minz, fa);
+    du = 0.f;
+    dv = 0.f;
+    if (vis) {
+        float inv = __frcp_rn((float)__float_as_int(r[PL::count]));
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch) dt[ch] = __fmaf_rn(r[ch], inv, dt[ch]);
+    }
+    if (!(vis || spatial_all)) return;
+    float tr = qx + 1 < lw ? induced<C>(pack, (uint64_t)pix + 1, Z, fa, tau) : 0.f;
+    float tl = qx > 0 ? induced<C>(pack, (uint64_t)pix - 1, Z, fa, tau) : 0.f;
+    float td = qy + 1 < lh ? induced<C>(pack, (uint64_t)pix + lw, Z, fa, tau) : 0.f;
+    float tu = qy > 0 ? induced<C>(pack, (uint64_t)pix - lw, Z, fa, tau) : 0.f;
+    du = tr - tl;
+    dv = td - tu;
+}
+
+#ifndef ADOP_BWD_SCALAR
+#define ADOP_BWD_SCALAR 1
+#endif
+#ifndef ADOP_PPL4
+#define ADOP_PPL4 4
+#endif
 
 template <int C, typename S, int PPL>
 __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, const float* __restrict__ ys,
@@ -445,24 +501,30 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
                 for (int l = 0; l < L; ++l) {
                     int qx = 0, qy = 0;
                     uint32_t pix = 0;
-                    if (!layer_pixel(c, l, p.u0, p.v0, qx, qy, pix)) continue;
-                    const float* r = pack + (uint64_t)pix * PL::stride;
-                    float minz = r[PL::minz];
-                    bool vis = p.Z <= __fmul_rn(minz, fa);
-                    if (vis) {
-                        float inv = __frcp_rn((float)__float_as_int(r[PL::count]));
-#pragma unroll
-                        for (int ch = 0; ch < C; ++ch) dt[k][ch] = __fmaf_rn(r[ch], inv, dt[k][ch]);
-                    }
-                    if (!(vis || spatial_all)) continue;
+                    bool in = layer_pixel(c, l, p.u0, p.v0, qx, qy, pix);
                     const int lw = c.lw[l], lh = c.lh[l];
-                    float tr = qx + 1 < lw ? induced<C>(pack, (uint64_t)pix + 1, p.Z, fa, tau[k]) : 0.f;
-                    float tl = qx > 0 ? induced<C>(pack, (uint64_t)pix - 1, p.Z, fa, tau[k]) : 0.f;
-                    float td = qy + 1 < lh ? induced<C>(pack, (uint64_t)pix + lw, p.Z, fa, tau[k]) : 0.f;
-                    float tu = qy > 0 ? induced<C>(pack, (uint64_t)pix - lw, p.Z, fa, tau[k]) : 0.f;
+                    float du = 0.f, dv = 0.f;
+#if ADOP_BWD_SCALAR
+                    uint64_t mk = ballot(in);
+                    if (mk == 0) continue;
+                    const int ld = __builtin_ctzll(mk);
+                    const uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pix, ld);
+                    const bool uni = ballot(in && pix != p0) == 0;
+                    if (!in) continue;
+                    if (uni) {
+                        const int ux = __builtin_amdgcn_readlane(qx, ld);
+                        const int uy = __builtin_amdgcn_readlane(qy, ld);
+                        point_layer<C>(pack, p0, ux, uy, lw, lh, p.Z, fa, spatial_all, tau[k], dt[k], du, dv);
+                    } else {
+                        point_layer<C>(pack, pix, qx, qy, lw, lh, p.Z, fa, spatial_all, tau[k], dt[k], du, dv);
+                    }
+#else
+                    if (!in) continue;
+                    point_layer<C>(pack, pix, qx, qy, lw, lh, p.Z, fa, spatial_all, tau[k], dt[k], du, dv);
+#endif
                     const float s = 0.5f * layer_scale(l);
-                    gu = __fmaf_rn(tr - tl, s, gu);
-                    gv = __fmaf_rn(td - tu, s, gv);
+                    gu = __fmaf_rn(du, s, gu);
+                    gv = __fmaf_rn(dv, s, gv);
                 }
                 if (gu == 0.f && gv == 0.f) continue;
                 any = true;
@@ -610,7 +672,7 @@ static hipError_t forward_impl(const FwdArgs& a, hipStream_t st) {
 
 template <int C, typename S>
 static hipError_t backward_impl(const BwdArgs& a, hipStream_t st) {
-    constexpr int PPL = C <= 4 ? 4 : 2;
+    constexpr int PPL = C <= 4 ? ADOP_PPL4 : 2;
     size_t lds = (size_t)4 * a.V * 16 * sizeof(double);
     dim3 gn((unsigned)std::min<int64_t>((a.max_layer_pixels + 255) / 256, 1024), (unsigned)(a.V * a.L));
     a.timer.mark(kKPack, 0, st);
@@ -629,7 +691,7 @@ static hipError_t backward_impl(const BwdArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-int backward_points_per_group(int C) { return kBlock * (C <= 4 ? 4 : 2); }
+int backward_points_per_group(int C) { return kBlock * (C <= 4 ? ADOP_PPL4 : 2); }
 
 #define ADOP_DISPATCH_C(FN, S, ARGS, ST)            \
     switch (ARGS.C) {                               \

@@ -101,8 +101,11 @@ def test_pose_descent(env):
     say("pose descent")
     dev = torch.device("cuda:0")
     rng = np.random.default_rng(8)
-    pos, feat = synth.planes(30, 20000, 3, 9, box=1.5, half_lo=0.4, half_hi=1.0)
-    feat = np.clip(feat + 0.0, 0, 1).astype(np.float32)
+    pos, _ = synth.planes(30, 20000, 3, 9, box=1.5, half_lo=0.4, half_hi=1.0)
+    # smooth texture so that every pyramid layer carries structure
+    pp = pos.astype(np.float64)
+    feat = np.stack([0.5 + 0.5 * np.sin(3.0 * pp[:, 0] + 1.0), 0.5 + 0.5 * np.cos(2.5 * pp[:, 1]),
+                     0.5 + 0.5 * np.sin(2.0 * pp[:, 2] + pp[:, 0])], axis=1).astype(np.float32)
     cam = synth.orbit_cameras(1, 5.0, 10, width=160, height=120, f=140.0, kmax=0.0)[0]
     scene = adop.Scene.prepare(ctx, torch.from_numpy(pos).to(dev), torch.from_numpy(feat).to(dev))
     L = 4
@@ -128,14 +131,15 @@ def test_pose_descent(env):
         return float(ang), float(np.linalg.norm(c1 - c0))
 
     e0 = pose_err()
-    lr = np.array([2e-3, 2e-3, 2e-3, 2e-4, 2e-4, 2e-4])
-    for it in range(60):
+    # sign-descent with decaying steps, separately for translation / rotation
+    lr = np.array([4e-3, 4e-3, 4e-3, 8e-4, 8e-4, 8e-4])
+    for it in range(120):
         outs = rast(scene.x, scene.y, scene.z, scene.feat, intr, tan)
         loss = sum((o - t).abs().mean() for o, t in zip(outs, target))
         loss.backward()
         with torch.no_grad():
             g = tan.grad.double().cpu().numpy()[0]
-            step = -lr * g / (np.abs(g).max() + 1e-30) * 5
+            step = -lr * np.sign(g) * (0.97 ** it)
             tan.copy_(torch.from_numpy(step[None]).to(dev))
             tan.grad = None
         rast.apply_tangent(tan)
