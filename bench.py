@@ -51,15 +51,16 @@ def algorithmic_bytes(n, C, s, phi, P):
 
 
 def l1_grad(frame, target):
-    """dL/dI of L = sum_l mean |I_l - T_l| (one view)."""
+    """dL/dI of L = sum over views and layers of mean |I - T|."""
     import torch
     G = torch.empty_like(frame.images)
     C = frame.channels
-    for l in range(frame.layers):
-        o = int(frame.offsets[0, l])
-        w, h = frame.cams[0].width >> l, frame.cams[0].height >> l
-        sl = slice(C * o, C * (o + w * h))
-        G[sl] = torch.sign(frame.images[sl] - target[sl]) / float(C * w * h)
+    for v in range(len(frame.cams)):
+        for l in range(frame.layers):
+            o = int(frame.offsets[v, l])
+            w, h = frame.cams[v].width >> l, frame.cams[v].height >> l
+            sl = slice(C * o, C * (o + w * h))
+            G[sl] = torch.sign(frame.images[sl] - target[sl]) / float(C * w * h)
     return G
 
 
@@ -83,16 +84,83 @@ def cpu_baseline(scene_np, n_sample):
                       f"forward), float64 oracle, one thread"}
 
 
+def serve_bench(args):
+    """Serving: a resident 50M-point BF16 scene, Poisson arrivals of
+    mixed-resolution novel views; the continuous-batching graph server vs
+    the plain unbatched FP32 renderer on the same trace."""
+    import numpy as np
+    import torch
+    from paper_2110_06635_amd import adop, serve, synth
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    s = synth.config5_scene(n=args.serve_points)
+    log(f"generated {s.name} in {time.time() - t0:.1f}s")
+    ctx = adop.Context(0)
+    pos = torch.from_numpy(s.pos).to(dev)
+    raw, _ = synth.storage(s.feat, "bf16")
+    scene16 = adop.Scene.prepare(ctx, pos, torch.from_numpy(raw.view(np.int16)).to(dev).view(torch.bfloat16),
+                                 adop.BF16)
+    scene32 = adop.Scene.prepare(ctx, pos, torch.from_numpy(s.feat).to(dev), adop.F32)
+    del pos
+    trace = synth.config5_requests(args.serve_warmup + args.serve_requests, rate=args.serve_rate)
+    results = {}
+    for name, scene, be_cls, kw in (
+            ("batched", scene16, serve.GpuBackend, dict(max_batch=args.serve_batch, max_inflight=3)),
+            ("plain_fp32", scene32, serve.PlainBackend, dict(max_batch=1, max_inflight=1))):
+        be = be_cls(ctx, scene, layers=4)
+        srv = serve.Server(be, args.serve_budget_gib << 30, **kw)
+        # capture every (class, batch size, lane) slot before the trace
+        for (w, h) in synth.SERVE_CLASSES:
+            cam = synth.serve_camera(np.random.default_rng(1), w, h)
+            for b in range(1, kw["max_batch"] + 1):
+                for lane in range(kw["max_inflight"]):
+                    hnd = be.launch((w, h), [cam] * b, lane)
+                    be.finish(hnd)
+        torch.cuda.synchronize()
+        srv.start()
+        log(f"serving {name}: {len(trace)} requests at {args.serve_rate}/s")
+        reqs = serve.replay(srv, trace, warmup=args.serve_warmup)
+        srv.stop()
+        measured = {r.rid for r in reqs}
+        srv.completed = [r for r in srv.completed if r.rid in measured]
+        results[name] = srv.stats()
+        del srv, be
+        torch.cuda.empty_cache()
+    b, p = results["batched"], results["plain_fp32"]
+    line = {
+        "metric": "p99 render latency, mixed-resolution novel views (50M points resident, 200 req/s)",
+        "value": b["p99_ms"], "unit": "ms", "higher_is_better": False, "n_gpus": 1,
+        "data": "synthetic", "dtype": "bf16 features, f32 accumulation",
+        "config": {"workload": s.name, "points": s.n, "layers": 4, "classes": synth.SERVE_CLASSES,
+                   "class_weights": synth.SERVE_WEIGHTS, "rate_per_s": args.serve_rate,
+                   "requests": args.serve_requests, "warmup": args.serve_warmup,
+                   "max_batch": args.serve_batch},
+        "batched": b, "baseline_plain_fp32_unbatched": p,
+        "p99_speedup_vs_plain": p["p99_ms"] / b["p99_ms"] if b["p99_ms"] > 0 else None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=100_000_000)
-    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"])
+    ap.add_argument("--workload", default="gmm100m", choices=["gmm100m", "planes10m", "multiview30m"],
+                    help="gmm100m: the headline workload; planes10m: 10M points on 200 planes; "
+                         "multiview30m: 30M points x 16 views, 8 BF16 channels, one fused launch per pass")
+    ap.add_argument("--n", type=int, default=0, help="override the point count")
+    ap.add_argument("--dtype", default="", choices=["", "f32", "bf16", "f16"])
     ap.add_argument("--variants", default="bf16,f16", help="extra feature storage types to time")
     ap.add_argument("--cpu-sample", type=int, default=4_000_000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve", action="store_true", help="run the serving benchmark instead")
+    ap.add_argument("--serve-points", type=int, default=50_000_000)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=100)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-batch", type=int, default=4)
+    ap.add_argument("--serve-budget-gib", type=int, default=96)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -100,6 +168,10 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(multi-GPU sharding is described in DESIGN.md, not built)"}))
         sys.exit(2)
+
+    if args.serve:
+        serve_bench(args)
+        return
 
     import numpy as np
     import torch
@@ -115,7 +187,17 @@ def main():
         log(f"copy probe: {nb} bytes read, {nb} bytes written")
         del src, dst
     t0 = time.time()
-    s = synth.config3(n=args.n)
+    if args.workload == "gmm100m":
+        s = synth.config3(n=args.n or 100_000_000)
+        args.dtype = args.dtype or "f32"
+    elif args.workload == "planes10m":
+        per = (args.n or 10_000_000) // 200
+        s = synth.config2(per_plane=per)
+        args.dtype = args.dtype or "f32"
+    else:
+        s = synth.config4(n=args.n or 30_000_000)
+        args.dtype = args.dtype or "bf16"
+    V = len(s.cams)
     log(f"generated {s.name} in {time.time() - t0:.1f}s")
     ctx = adop.Context(0)
     dev = torch.device("cuda:0")
@@ -134,13 +216,13 @@ def main():
         del pos, feat
         torch.cuda.synchronize()
         frame = adop.Frame(s.cams, s.layers, C, dev)
-        ws = ctx.workspace(C, 1, frame.pixels)
+        ws = ctx.workspace(C, V, frame.pixels)
         adop.render_forward(ctx, scene, frame.cams, s.layers, alpha=s.alpha, frame=frame, workspace=ws)
         G = l1_grad(frame, target)
         out = (torch.empty((scene.n, C), dtype=torch.float32, device=dev),
                torch.empty((3, scene.n), dtype=torch.float32, device=dev),
-               torch.empty((1, 6), dtype=torch.float64, device=dev),
-               torch.empty((1, 9), dtype=torch.float64, device=dev))
+               torch.empty((V, 6), dtype=torch.float64, device=dev),
+               torch.empty((V, 9), dtype=torch.float64, device=dev))
 
         def step():
             adop.render_forward(ctx, scene, frame.cams, s.layers, alpha=s.alpha, frame=frame, workspace=ws)
@@ -177,7 +259,7 @@ def main():
     log(f"timing {args.dtype}: warmup {args.warmup}, steps {args.steps}")
     r = run(args.dtype, args.steps, args.warmup, timing=True)
     n = s.n
-    value = n / (r["ms"] * 1e-3)
+    value = n * V / (r["ms"] * 1e-3)
     ab = algorithmic_bytes(n, C, r["s"], r["phi"], r["pixels"])
     kern = {k: {"avg_ms": (v[0] / v[1]) if v[1] else 0.0, "launches": v[1]} for k, v in r["kern"].items()}
     dom = max(kern, key=lambda k: kern[k]["avg_ms"])
@@ -191,16 +273,17 @@ def main():
         log(f"timing variant {vd}")
         rv = run(vd, max(3, args.steps // 2), 2, timing=False)
         abv = algorithmic_bytes(n, C, rv["s"], rv["phi"], rv["pixels"])
-        variants[vd] = {"value": n / (rv["ms"] * 1e-3), "ms_per_step": round(rv["ms"], 4),
+        variants[vd] = {"value": n * V / (rv["ms"] * 1e-3), "ms_per_step": round(rv["ms"], 4),
                         "step_frac_of_hbm_roofline": round(sum(abv.values()) / (rv["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and V == 1:
         log(f"cpu baseline on {args.cpu_sample} points")
         cpu = cpu_baseline(s, args.cpu_sample)
     line = {
-        "metric": "points/sec fwd+bwd at 100M pts 1080p (% HBM roofline); p99 render latency",
+        "metric": ("points/sec fwd+bwd at 100M pts 1080p (% HBM roofline); p99 render latency"
+                   if args.workload == "gmm100m" else f"point-views/sec fwd+bwd ({args.workload})"),
         "value": value,
-        "unit": "points/s",
+        "unit": "points/s" if V == 1 else "point-views/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -209,10 +292,11 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
+        "feature_storage": args.dtype,
         "data": "synthetic",
         "config": {"workload": s.name, "points": n, "resolution": "1920x1080", "layers": s.layers,
                    "channels": C, "feature_storage": args.dtype, "alpha": s.alpha,
-                   "loss": "L1 to seeded U[0,1] target", "views": 1},
+                   "loss": "L1 to seeded U[0,1] target", "views": V},
         "step_frac_of_hbm_roofline": round(step_bytes / (r["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "step_algorithmic_bytes": int(step_bytes),
         "phi": round(r["phi"], 5),

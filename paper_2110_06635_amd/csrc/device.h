@@ -35,6 +35,37 @@ struct alignas(16) ViewRec {
 };
 static_assert(sizeof(ViewRec) == 256, "ViewRec must be 256 bytes");
 
+// The constants of one view as the kernels hold them (scalar registers when
+// the view is wave-uniform); layer tables indexed with constant l only.
+struct Cam {
+    float fx, fy, cx, cy, k1, k2, k3, p1, p2, znear, r2max;
+    float R[9];
+    float t[3];
+    int w, h;
+    int lw[kMaxLayers];
+    int lh[kMaxLayers];
+    uint32_t base[kMaxLayers];
+};
+
+__device__ __forceinline__ Cam load_cam(const ViewRec* __restrict__ v) {
+    Cam c;
+    c.fx = v->fx; c.fy = v->fy; c.cx = v->cx; c.cy = v->cy;
+    c.k1 = v->k1; c.k2 = v->k2; c.k3 = v->k3; c.p1 = v->p1; c.p2 = v->p2;
+    c.znear = v->znear; c.r2max = v->r2max;
+    c.w = v->w; c.h = v->h;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) c.R[k] = v->R[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c.t[k] = v->t[k];
+#pragma unroll
+    for (int l = 0; l < kMaxLayers; ++l) {
+        c.lw[l] = v->lw[l];
+        c.lh[l] = v->lh[l];
+        c.base[l] = v->base[l];
+    }
+    return c;
+}
+
 // Layer scale 2^-l as an exact constant.
 __device__ __forceinline__ float layer_scale(int l) {
     return __int_as_float((127 - l) << 23);
@@ -52,7 +83,8 @@ struct Proj {
 // D = 1 + k1 r2 + k2 r2^2 + k3 r2^3,
 // x_d = a D + 2 p1 a b + p2 (r2 + 2a^2), y_d = b D + 2 p2 a b + p1 (r2 + 2b^2),
 // u0 = fx x_d + cx, v0 = fy y_d + cy.
-__device__ __forceinline__ Proj project(const ViewRec& c, float x, float y, float z) {
+template <typename CamT>
+__device__ __forceinline__ Proj project(const CamT& c, float x, float y, float z) {
     Proj p;
     float X = __fmaf_rn(c.R[0], x, __fmaf_rn(c.R[1], y, __fmaf_rn(c.R[2], z, c.t[0])));
     float Y = __fmaf_rn(c.R[3], x, __fmaf_rn(c.R[4], y, __fmaf_rn(c.R[5], z, c.t[1])));
@@ -77,7 +109,8 @@ __device__ __forceinline__ Proj project(const ViewRec& c, float x, float y, floa
 
 // Pixel of layer l (Eq. round + Eq. boundscheck): rint(u0 * 2^-l), in
 // [0,w_l) x [0,h_l).  Returns the frame pixel index in *pix.
-__device__ __forceinline__ bool layer_pixel(const ViewRec& c, int l, float u0, float v0,
+template <typename CamT>
+__device__ __forceinline__ bool layer_pixel(const CamT& c, int l, float u0, float v0,
                                             int& px, int& py, uint32_t& pix) {
     float s = layer_scale(l);
     float fx = __builtin_rintf(__fmul_rn(u0, s));
@@ -87,6 +120,20 @@ __device__ __forceinline__ bool layer_pixel(const ViewRec& c, int l, float u0, f
     px = in ? (int)fx : 0;
     py = in ? (int)fy : 0;
     pix = c.base[l] + (uint32_t)py * (uint32_t)lw + (uint32_t)px;
+    return in;
+}
+
+// The same as layer_pixel with the layer size and first pixel given (for
+// loops over layers that are not unrolled: w_l = w >> l, h_l = h >> l).
+__device__ __forceinline__ bool layer_pixel_at(int l, int lw, int lh, uint32_t base, float u0, float v0,
+                                               int& px, int& py, uint32_t& pix) {
+    float s = layer_scale(l);
+    float fx = __builtin_rintf(__fmul_rn(u0, s));
+    float fy = __builtin_rintf(__fmul_rn(v0, s));
+    bool in = fx >= 0.0f && fx < (float)lw && fy >= 0.0f && fy < (float)lh;
+    px = in ? (int)fx : 0;
+    py = in ? (int)fy : 0;
+    pix = base + (uint32_t)py * (uint32_t)lw + (uint32_t)px;
     return in;
 }
 
@@ -289,6 +336,25 @@ __device__ __forceinline__ int table_slot(uint32_t* tkey, uint32_t pix, int* ful
         h = (h + 1) & mask;
     }
     *full = 1;
+    return -1;
+}
+
+// Direct-mapped variant with two fixed probes (home slot and its neighbour):
+// no loop; -1 when both are taken by other pixels.
+template <int BITS>
+__device__ __forceinline__ int table_slot2(uint32_t* tkey, uint32_t pix) {
+    constexpr uint32_t mask = (1u << BITS) - 1;
+    uint32_t h = hash_slot<BITS>(pix);
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        uint32_t k = __hip_atomic_load(&tkey[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (k == pix) return (int)h;
+        if (k == kEmptySlot) {
+            uint32_t old = atomicCAS(&tkey[h], kEmptySlot, pix);
+            if (old == kEmptySlot || old == pix) return (int)h;
+        }
+        h = (h + 1) & mask;
+    }
     return -1;
 }
 

@@ -5,7 +5,7 @@
 //   k_depth      project every point into every view and layer, 64-bit
 //                atomic minimum of (depth bits << 32 | original index)
 //   k_accum      fuzzy depth test z <= (1+alpha) min_z (Eq. depthtest),
-//                FP32 atomic sums of the features and an integer count
+//                FP32 sums of the features and an integer count
 //   k_normalize  mean of the blend set or the background (Eq. blend)
 // Backward:
 //   k_pack       per-pixel record {G, <G,I>, min_z, n} for the gathers
@@ -16,14 +16,47 @@
 //                sums in FP64 with a fixed reduction order
 //   k_reduce     fixed-order FP64 sum of the per-workgroup partials
 //
-// Contention handling: a wave whose active lanes all hit one pixel reduces
-// in registers (DPP) and issues one atomic; otherwise lanes test the current
-// key before the atomic minimum (keys only decrease, so a stale read can only
-// let an unnecessary atomic through).
+// Every workgroup of a point kernel owns one contiguous range of the
+// Morton-ordered points (a compact region of space).  The depth and
+// accumulation passes keep a workgroup-private direct-mapped table in LDS
+// (pixel -> minimum key, or pixel -> feature sums and count) for the whole
+// range and write it to global memory with atomics at the end; a pixel whose
+// slot is taken goes straight to the global atomics.  Inside a wave, lanes
+// that hit one pixel are combined first (DPP) so one lane updates for them.
 #include "device.h"
 #include "launch.h"
 
 namespace adop {
+
+#ifndef ADOP_MAX_GROUPS
+#define ADOP_MAX_GROUPS 6
+#endif
+#ifndef ADOP_MIN_GROUP
+#define ADOP_MIN_GROUP 3
+#endif
+#ifndef ADOP_ACC_BITS4
+#define ADOP_ACC_BITS4 9
+#endif
+#ifndef ADOP_DEPTH_BITS
+#define ADOP_DEPTH_BITS 12
+#endif
+#ifndef ADOP_DEPTH_WAVEMIN
+#define ADOP_DEPTH_WAVEMIN 1
+#endif
+// ADOP_DEPTH_TABLE 1: LDS table per workgroup; 0 (default, faster on the
+// benchmark scene): read the global keys of all layers first, then compare
+// and issue the (rare) atomic minimum
+#ifndef ADOP_DEPTH_TABLE
+#define ADOP_DEPTH_TABLE 0
+#endif
+// ADOP_ACC_TABLE 1: LDS table per workgroup; 0: wave groups go straight to
+// global atomics
+#ifndef ADOP_ACC_TABLE
+#define ADOP_ACC_TABLE 1
+#endif
+#ifndef ADOP_PPL4
+#define ADOP_PPL4 4
+#endif
 
 // ---------------------------------------------------------------------------
 // forward
@@ -45,18 +78,12 @@ __global__ void __launch_bounds__(256) k_clear(uint64_t* __restrict__ keys, int3
 }
 
 // ---- depth pass -----------------------------------------------------------
-// Per-workgroup LDS table pixel -> minimum key.  A wave whose active lanes all
-// hit one pixel takes the wave minimum (DPP) and updates once; otherwise each
-// lane updates.  Updates read the current value first and issue the atomic
-// minimum only when they would lower it (keys only decrease, so a stale read
-// can only let an unnecessary atomic through).
-constexpr int kDepthBits = 11;
+constexpr int kDepthBits = ADOP_DEPTH_BITS;
 constexpr int kDepthH = 1 << kDepthBits;
 
 struct DepthTable {
     uint32_t key[kDepthH];
     uint64_t val[kDepthH];
-    int full;
 };
 
 __device__ __forceinline__ void global_min(uint64_t* __restrict__ gkeys, uint32_t pix, uint64_t k) {
@@ -64,8 +91,11 @@ __device__ __forceinline__ void global_min(uint64_t* __restrict__ gkeys, uint32_
     if (k < cur) atomic_min_u64(gkeys + pix, k);
 }
 
+// Lower the pixel's minimum to k: read first, update only when it would
+// lower the value (keys only decrease, so a stale read can only let an
+// unnecessary atomic through).
 __device__ __forceinline__ void table_min(DepthTable& t, uint64_t* __restrict__ gkeys, uint32_t pix, uint64_t k) {
-    int slot = table_slot<kDepthBits>(t.key, pix, &t.full);
+    int slot = table_slot2<kDepthBits>(t.key, pix);
     if (slot < 0) {
         global_min(gkeys, pix, k);
         return;
@@ -76,6 +106,7 @@ __device__ __forceinline__ void table_min(DepthTable& t, uint64_t* __restrict__ 
 
 __device__ __forceinline__ void depth_update(bool in, uint32_t pix, uint64_t key, DepthTable& t,
                                              uint64_t* __restrict__ gkeys) {
+#if ADOP_DEPTH_WAVEMIN
     uint64_t m = ballot(in);
     if (m == 0) return;
     int leader = __builtin_ctzll(m);
@@ -83,9 +114,10 @@ __device__ __forceinline__ void depth_update(bool in, uint32_t pix, uint64_t key
     if (ballot(in && pix != p0) == 0) {
         uint64_t k = wave_min_u64(in ? key : ~0ull);
         if (lane_id() == leader) table_min(t, gkeys, p0, k);
-    } else if (in) {
-        table_min(t, gkeys, pix, key);
+        return;
     }
+#endif
+    if (in) table_min(t, gkeys, pix, key);
 }
 
 __device__ __forceinline__ void depth_table_clear(DepthTable& t) {
@@ -98,22 +130,71 @@ __device__ __forceinline__ void depth_table_clear(DepthTable& t) {
 __device__ __forceinline__ void depth_table_flush(DepthTable& t, uint64_t* __restrict__ gkeys) {
     for (int j = threadIdx.x; j < kDepthH; j += blockDim.x) {
         uint32_t k = t.key[j];
-        if (k != kEmptySlot) {
-            global_min(gkeys, k, t.val[j]);
-            t.key[j] = kEmptySlot;
-            t.val[j] = ~0ull;
-        }
+        if (k != kEmptySlot) global_min(gkeys, k, t.val[j]);
     }
 }
 
+__device__ __forceinline__ void depth_point(const Cam& c, int L, bool live, float x, float y, float z, uint32_t oi,
+                                            DepthTable* t, uint64_t* __restrict__ keys) {
+    Proj p = project(c, x, y, z);
+    bool ok = live && p.ok;
+    uint64_t key = ((uint64_t)__float_as_uint(p.Z) << 32) | oi;
+#if ADOP_DEPTH_TABLE
+#pragma unroll
+    for (int l = 0; l < kMaxLayers; ++l) {
+        if (l >= L) break;
+        int px = 0, py = 0;
+        uint32_t pix = 0;
+        bool in = ok && layer_pixel(c, l, p.u0, p.v0, px, py, pix);
+        depth_update(in, pix, key, *t, keys);
+    }
+#else
+    uint32_t pix[kMaxLayers];
+    bool in[kMaxLayers];
+    uint64_t cur[kMaxLayers];
+#pragma unroll
+    for (int l = 0; l < kMaxLayers; ++l) {
+        pix[l] = 0;
+        in[l] = false;
+        cur[l] = 0;
+        if (l < L) {
+            int px = 0, py = 0;
+            in[l] = ok && layer_pixel(c, l, p.u0, p.v0, px, py, pix[l]);
+            if (in[l]) cur[l] = load_relaxed_u64(keys + pix[l]);
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < kMaxLayers; ++l) {
+        if (l >= L) break;
+        bool want = in[l] && key < cur[l];
+        uint64_t m = ballot(want);
+        if (m == 0) continue;
+        int leader = __builtin_ctzll(m);
+        uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pix[l], leader);
+        if (ballot(want && pix[l] != p0) == 0) {
+            uint64_t k = wave_min_u64(want ? key : ~0ull);
+            if (lane_id() == leader) atomic_min_u64(keys + p0, k);
+        } else if (want) {
+            atomic_min_u64(keys + pix[l], key);
+        }
+    }
+#endif
+}
+
+template <bool SINGLE>
 __global__ void __launch_bounds__(256) k_depth(const float* __restrict__ xs, const float* __restrict__ ys,
                                                const float* __restrict__ zs, const int32_t* __restrict__ orig,
                                                int64_t n, const ViewRec* __restrict__ views, int V, int L,
                                                uint64_t* __restrict__ keys) {
-    __shared__ DepthTable t;
-    depth_table_clear(t);
-    if (threadIdx.x == 0) t.full = 0;
+#if ADOP_DEPTH_TABLE
+    __shared__ DepthTable table;
+    DepthTable* t = &table;
+    depth_table_clear(table);
     __syncthreads();
+#else
+    DepthTable* t = nullptr;
+#endif
+    const Cam c0 = load_cam(views);
     RangeMap m = range_map(n, kBlock);
     for (int64_t c = m.c0; c < m.c1; ++c) {
         int64_t i = c * kBlock + threadIdx.x;
@@ -126,60 +207,34 @@ __global__ void __launch_bounds__(256) k_depth(const float* __restrict__ xs, con
             z = zs[i];
             oi = (uint32_t)orig[i];
         }
-        for (int v = 0; v < V; ++v) {
-            const ViewRec& cam = views[v];
-            Proj p = project(cam, x, y, z);
-            bool ok = live && p.ok;
-            uint64_t key = ((uint64_t)__float_as_uint(p.Z) << 32) | oi;
-            for (int l = 0; l < L; ++l) {
-                int px = 0, py = 0;
-                uint32_t pix = 0;
-                bool in = ok && layer_pixel(cam, l, p.u0, p.v0, px, py, pix);
-                depth_update(in, pix, key, t, keys);
-            }
-        }
-        __syncthreads();
-        if (t.full) {
-            depth_table_flush(t, keys);
-            __syncthreads();
-            if (threadIdx.x == 0) t.full = 0;
-            __syncthreads();
+        if (SINGLE) {
+            depth_point(c0, L, live, x, y, z, oi, t, keys);
+        } else {
+            for (int v = 0; v < V; ++v) depth_point(load_cam(views + v), L, live, x, y, z, oi, t, keys);
         }
     }
+#if ADOP_DEPTH_TABLE
     __syncthreads();
-    depth_table_flush(t, keys);
+    depth_table_flush(table, keys);
+#endif
 }
 
 // ---- accumulation pass ----------------------------------------------------
-// Per-workgroup LDS table pixel -> (feature sums, count).  Inside a wave the
-// passing lanes are grouped by pixel (leader loop: the first remaining lane's
-// pixel, the ballot of lanes sharing it, DPP sums) so that one lane adds a
-// group's total; lanes left when the groups become small add individually.
-#ifndef ADOP_MAX_GROUPS
-#define ADOP_MAX_GROUPS 6
-#endif
-#ifndef ADOP_MIN_GROUP
-#define ADOP_MIN_GROUP 3
-#endif
-#ifndef ADOP_ACC_BITS4
-#define ADOP_ACC_BITS4 10
-#endif
 constexpr int kMaxGroups = ADOP_MAX_GROUPS;
 constexpr int kMinGroup = ADOP_MIN_GROUP;
 
 template <int C> struct AccTable {
-    static constexpr int bits = C <= 4 ? ADOP_ACC_BITS4 : (C <= 8 ? ADOP_ACC_BITS4 - 1 : ADOP_ACC_BITS4 - 2);
+    static constexpr int bits = !ADOP_ACC_TABLE ? 1 : C <= 4 ? ADOP_ACC_BITS4 : (C <= 8 ? ADOP_ACC_BITS4 - 1 : ADOP_ACC_BITS4 - 2);
     static constexpr int H = 1 << bits;
     uint32_t key[H];
     float sum[C][H];
     int32_t cnt[H];
-    int full;
 };
 
 template <int C>
 __device__ __forceinline__ void table_add(AccTable<C>& t, float* __restrict__ sums, int32_t* __restrict__ counts,
                                           uint32_t pix, const float (&s)[C], int32_t k) {
-    int slot = table_slot<AccTable<C>::bits>(t.key, pix, &t.full);
+    int slot = ADOP_ACC_TABLE ? table_slot2<AccTable<C>::bits>(t.key, pix) : -1;
     if (slot < 0) {
         float* dst = sums + (uint64_t)pix * C;
 #pragma unroll
@@ -193,10 +248,14 @@ __device__ __forceinline__ void table_add(AccTable<C>& t, float* __restrict__ su
     __hip_atomic_fetch_add(&t.cnt[slot], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Lanes whose point passes are grouped by pixel: the first remaining lane's
+// pixel, the ballot of the lanes sharing it, DPP sums; groups smaller than
+// kMinGroup (and lanes left after kMaxGroups) add individually.
 template <int C>
 __device__ __forceinline__ void accum_update(bool pass, uint32_t pix, const float (&f)[C], AccTable<C>& t,
                                              float* __restrict__ sums, int32_t* __restrict__ counts) {
     uint64_t rem = ballot(pass);
+    if (rem == 0) return;
     const int lane = lane_id();
 #pragma unroll 1
     for (int it = 0; it < kMaxGroups && rem != 0; ++it) {
@@ -232,18 +291,43 @@ __device__ __forceinline__ void acc_table_flush(AccTable<C>& t, float* __restric
         if (k != kEmptySlot) {
             float* dst = sums + (uint64_t)k * C;
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                atomic_add_f32(dst + c, t.sum[c][j]);
-                t.sum[c][j] = 0.f;
-            }
+            for (int c = 0; c < C; ++c) atomic_add_f32(dst + c, t.sum[c][j]);
             atomic_add_i32(counts + k, t.cnt[j]);
-            t.cnt[j] = 0;
-            t.key[j] = kEmptySlot;
         }
     }
 }
 
-template <int C, typename S>
+template <int C>
+__device__ __forceinline__ void accum_point(const Cam& c, int L, float fa, bool live, float x, float y, float z,
+                                            const float (&f)[C], const uint32_t* __restrict__ keys32, AccTable<C>& t,
+                                            float* __restrict__ sums, int32_t* __restrict__ counts) {
+    Proj p = project(c, x, y, z);
+    bool ok = live && p.ok;
+    // all layers' front depths are gathered before any update, so the
+    // gathers are in flight together
+    uint32_t pix[kMaxLayers];
+    bool in[kMaxLayers];
+    float mz[kMaxLayers];
+#pragma unroll
+    for (int l = 0; l < kMaxLayers; ++l) {
+        pix[l] = 0;
+        in[l] = false;
+        mz[l] = 0.f;
+        if (l < L) {
+            int px = 0, py = 0;
+            in[l] = ok && layer_pixel(c, l, p.u0, p.v0, px, py, pix[l]);
+            if (in[l]) mz[l] = __uint_as_float(keys32[2 * (uint64_t)pix[l] + 1]);
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < kMaxLayers; ++l) {
+        if (l >= L) break;
+        bool pass = in[l] && p.Z <= __fmul_rn(mz[l], fa);
+        accum_update<C>(pass, pix[l], f, t, sums, counts);
+    }
+}
+
+template <int C, typename S, bool SINGLE>
 __global__ void __launch_bounds__(256) k_accum(const float* __restrict__ xs, const float* __restrict__ ys,
                                                const float* __restrict__ zs, const void* __restrict__ feat,
                                                int64_t n, const ViewRec* __restrict__ views, int V, int L,
@@ -251,8 +335,8 @@ __global__ void __launch_bounds__(256) k_accum(const float* __restrict__ xs, con
                                                float* __restrict__ sums, int32_t* __restrict__ counts) {
     __shared__ AccTable<C> t;
     acc_table_clear<C>(t);
-    if (threadIdx.x == 0) t.full = 0;
     __syncthreads();
+    const Cam c0 = load_cam(views);
     RangeMap m = range_map(n, kBlock);
     for (int64_t c = m.c0; c < m.c1; ++c) {
         int64_t i = c * kBlock + threadIdx.x;
@@ -267,28 +351,11 @@ __global__ void __launch_bounds__(256) k_accum(const float* __restrict__ xs, con
             z = zs[i];
             load_feat<C, S>(feat, i, f);
         }
-        for (int v = 0; v < V; ++v) {
-            const ViewRec& cam = views[v];
-            Proj p = project(cam, x, y, z);
-            bool ok = live && p.ok;
-            for (int l = 0; l < L; ++l) {
-                int px = 0, py = 0;
-                uint32_t pix = 0;
-                bool in = ok && layer_pixel(cam, l, p.u0, p.v0, px, py, pix);
-                bool pass = false;
-                if (in) {
-                    float minz = __uint_as_float(keys32[2 * (uint64_t)pix + 1]);
-                    pass = p.Z <= __fmul_rn(minz, fa);
-                }
-                accum_update<C>(pass, pix, f, t, sums, counts);
-            }
-        }
-        __syncthreads();
-        if (t.full) {
-            acc_table_flush<C>(t, sums, counts);
-            __syncthreads();
-            if (threadIdx.x == 0) t.full = 0;
-            __syncthreads();
+        if (SINGLE) {
+            accum_point<C>(c0, L, fa, live, x, y, z, f, keys32, t, sums, counts);
+        } else {
+            for (int v = 0; v < V; ++v)
+                accum_point<C>(load_cam(views + v), L, fa, live, x, y, z, f, keys32, t, sums, counts);
         }
     }
     __syncthreads();
@@ -375,10 +442,10 @@ template <int C>
 __device__ __forceinline__ void load_rec(const float* __restrict__ pack, uint64_t q,
                                          float (&rec)[PackLayout<C>::stride]) {
     using PL = PackLayout<C>;
-    const float4* r = reinterpret_cast<const float4*>(pack + q * PL::stride);
+    const float4* r4 = reinterpret_cast<const float4*>(pack + q * PL::stride);
 #pragma unroll
     for (int k = 0; k < PL::stride / 4; ++k) {
-        float4 t4 = r[k];
+        float4 t4 = r4[k];
         rec[4 * k] = t4.x;
         rec[4 * k + 1] = t4.y;
         rec[4 * k + 2] = t4.z;
@@ -396,75 +463,141 @@ __device__ __forceinline__ float induced_rec(const float (&rec)[PackLayout<C>::s
 #pragma unroll
     for (int ch = 0; ch < C; ++ch) dot = __fmaf_rn(rec[ch], tau[ch], dot);
     float t = dot - rec[PL::gdot];
-    float factor;
-    if (nq == 0) {
-        factor = 1.0f;
-    } else if (Z > __fmul_rn(mq, fa)) {
-        factor = 0.0f;
-    } else if (__fmul_rn(Z, fa) < mq) {
-        factor = 1.0f;
-    } else {
-        factor = __frcp_rn((float)(nq + 1));
-    }
+    float factor = __builtin_amdgcn_rcpf((float)(nq + 1));
+    factor = (__fmul_rn(Z, fa) < mq) ? 1.0f : factor;
+    factor = (Z > __fmul_rn(mq, fa)) ? 0.0f : factor;
+    factor = (nq == 0) ? 1.0f : factor;
     return factor * t;
 }
 
+// A layer where the point is in its pixel's blend set (or every in-bounds
+// point with SPATIAL_ALL): the own record and the four neighbour records are
+// loaded together, then dtau += G/n (if vis) and dL/du, dL/dv.
 template <int C>
-__device__ __forceinline__ float induced(const float* __restrict__ pack, uint64_t q, float Z, float fa,
-                                         const float (&tau)[C]) {
-    float rec[PackLayout<C>::stride];
-    load_rec<C>(pack, q, rec);
-    return induced_rec<C>(rec, Z, fa, tau);
-}
-
-// One point at one layer: feature gradient and the layer's dL/du, dL/dv.
-// `pix`, `qx`, `qy` may be wave-uniform (all lanes on one pixel), in which
-// case every record load is a scalar load.
-template <int C>
-__device__ __forceinline__ void point_layer(const float* __restrict__ pack, uint32_t pix, int qx, int qy, int lw,
-                                            int lh, float Z, float fa, bool spatial_all, const float (&tau)[C],
-                                            float (&dt)[C], float& du, float& dv) {
+__device__ __forceinline__ void layer_work(const float* __restrict__ pack, uint32_t pix, int qx, int qy, int lw,
+                                           int lh, float Z, float fa, bool vis, const float (&tau)[C],
+                                           float (&dt)[C], float& du, float& dv) {
     using PL = PackLayout<C>;
-    const float* r = pack + (uint64_t)pix * PL::stride;
-    float minz = r[PL::minz];
-    bool vis = Z <= __fmul_rn(minz, fa);
-    du = 0.f;
-    dv = 0.f;
+    float own[PL::stride], rr[PL::stride], rl[PL::stride], rd[PL::stride], ru[PL::stride];
+    const bool hr = qx + 1 < lw, hl = qx > 0, hd = qy + 1 < lh, hu = qy > 0;
+    load_rec<C>(pack, pix, own);
+    load_rec<C>(pack, hr ? (uint64_t)pix + 1 : (uint64_t)pix, rr);
+    load_rec<C>(pack, hl ? (uint64_t)pix - 1 : (uint64_t)pix, rl);
+    load_rec<C>(pack, hd ? (uint64_t)pix + lw : (uint64_t)pix, rd);
+    load_rec<C>(pack, hu ? (uint64_t)pix - lw : (uint64_t)pix, ru);
     if (vis) {
-        float inv = __frcp_rn((float)__float_as_int(r[PL::count]));
+        float inv = __builtin_amdgcn_rcpf((float)__float_as_int(own[PL::count]));
 #pragma unroll
-        for (int ch = 0; ch < C; ++ch) dt[ch] = __fmaf_rn(r[ch], inv, dt[ch]);
+        for (int ch = 0; ch < C; ++ch) dt[ch] = __fmaf_rn(own[ch], inv, dt[ch]);
     }
-    if (!(vis || spatial_all)) return;
-    float tr = qx + 1 < lw ? induced<C>(pack, (uint64_t)pix + 1, Z, fa, tau) : 0.f;
-    float tl = qx > 0 ? induced<C>(pack, (uint64_t)pix - 1, Z, fa, tau) : 0.f;
-    float td = qy + 1 < lh ? induced<C>(pack, (uint64_t)pix + lw, Z, fa, tau) : 0.f;
-    float tu = qy > 0 ? induced<C>(pack, (uint64_t)pix - lw, Z, fa, tau) : 0.f;
+    float tr = hr ? induced_rec<C>(rr, Z, fa, tau) : 0.f;
+    float tl = hl ? induced_rec<C>(rl, Z, fa, tau) : 0.f;
+    float td = hd ? induced_rec<C>(rd, Z, fa, tau) : 0.f;
+    float tu = hu ? induced_rec<C>(ru, Z, fa, tau) : 0.f;
     du = tr - tl;
     dv = td - tu;
 }
 
-#ifndef ADOP_BWD_SCALAR
-#define ADOP_BWD_SCALAR 1
-#endif
-#ifndef ADOP_PPL4
-#define ADOP_PPL4 4
-#endif
+// One point in one view: dL/du0, dL/dv0 summed over layers, then the chain
+// through the projection; adds the 15 pose/intrinsics terms to acc (FP32).
+// The layer loop is not unrolled (it keeps the kernel within the instruction
+// cache); w_l = w >> l, h_l = h >> l and layer bases follow one another.
+template <int C>
+__device__ __forceinline__ void point_view(const Cam& c, int L, float fa, bool spatial_all,
+                                           const float* __restrict__ pack, bool live, float x, float y, float z,
+                                           const float (&tau)[C], float (&dt)[C], float (&dp)[3], float (&acc)[15],
+                                           bool& any) {
+    using PL = PackLayout<C>;
+    Proj p = project(c, x, y, z);
+    if (!(live && p.ok)) return;
+    float gu = 0.f, gv = 0.f;
+    uint32_t base = c.base[0];
+#pragma unroll 1
+    for (int l = 0; l < L; ++l) {
+        const int lw = c.w >> l, lh = c.h >> l;
+        int qx = 0, qy = 0;
+        uint32_t pix = 0;
+        const bool in = layer_pixel_at(l, lw, lh, base, p.u0, p.v0, qx, qy, pix);
+        base += (uint32_t)lw * (uint32_t)lh;
+        float mz = 0.f;
+        if (in) mz = pack[(uint64_t)pix * PL::stride + PL::minz];
+        const bool vis = in && p.Z <= __fmul_rn(mz, fa);
+        if (!(vis || (spatial_all && in))) continue;
+        float du = 0.f, dv = 0.f;
+        layer_work<C>(pack, pix, qx, qy, lw, lh, p.Z, fa, vis, tau, dt, du, dv);
+        const float s = 0.5f * layer_scale(l);
+        gu = __fmaf_rn(du, s, gu);
+        gv = __fmaf_rn(dv, s, gv);
+    }
+    if (gu == 0.f && gv == 0.f) return;
+    any = true;
+    const float a = p.a, b = p.b, r2 = p.r2, D = p.D;
+    const float Dp = __fmaf_rn(r2, __fmaf_rn(r2, 3.0f * c.k3, 2.0f * c.k2), c.k1);
+    const float xa = D + 2.0f * a * a * Dp + 2.0f * c.p1 * b + 6.0f * c.p2 * a;
+    const float xb = 2.0f * a * b * Dp + 2.0f * c.p1 * a + 2.0f * c.p2 * b;
+    const float yb = D + 2.0f * b * b * Dp + 6.0f * c.p1 * b + 2.0f * c.p2 * a;
+    const float gux = gu * c.fx, gvy = gv * c.fy;
+    const float ga = gux * xa + gvy * xb;
+    const float gb = gux * xb + gvy * yb;
+    const float iz = __builtin_amdgcn_rcpf(p.Z);
+    const float gcx = ga * iz, gcy = gb * iz, gcz = -(a * ga + b * gb) * iz;
+    dp[0] += c.R[0] * gcx + c.R[3] * gcy + c.R[6] * gcz;
+    dp[1] += c.R[1] * gcx + c.R[4] * gcy + c.R[7] * gcz;
+    dp[2] += c.R[2] * gcx + c.R[5] * gcy + c.R[8] * gcz;
+    const float au = gux * a + gvy * b;
+    const float r4 = r2 * r2;
+    acc[0] += gcx;
+    acc[1] += gcy;
+    acc[2] += gcz;
+    acc[3] += p.Y * gcz - p.Z * gcy;
+    acc[4] += p.Z * gcx - p.X * gcz;
+    acc[5] += p.X * gcy - p.Y * gcx;
+    acc[6] += gu * p.xd;
+    acc[7] += gv * p.yd;
+    acc[8] += gu;
+    acc[9] += gv;
+    acc[10] += au * r2;
+    acc[11] += au * r4;
+    acc[12] += au * r4 * r2;
+    acc[13] += gux * 2.0f * a * b + gvy * (r2 + 2.0f * b * b);
+    acc[14] += gux * (r2 + 2.0f * a * a) + gvy * 2.0f * a * b;
+}
 
-template <int C, typename S, int PPL>
+// The 15 terms of the PPL points of a lane (FP32, at most PPL terms each) are
+// widened to FP64 and summed over the wave in a fixed DPP order; each wave
+// owns its LDS slot, so the sum order is fixed for a fixed grid.
+__device__ __forceinline__ void reduce_terms(const float (&acc)[15], bool any, double* __restrict__ slot, int lane) {
+    if (ballot(any) == 0) return;
+#pragma unroll
+    for (int t = 0; t < 15; ++t) {
+        double s = wave_sum_f64((double)acc[t]);
+        if (lane == 0) slot[t] += s;
+    }
+}
+
+constexpr int kSuper = 4;   // chunks a lane sums in FP32 before widening (single view)
+
+template <int C, typename S, int PPL, bool SINGLE>
 __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, const float* __restrict__ ys,
                                                   const float* __restrict__ zs, const void* __restrict__ feat,
                                                   int64_t n, const ViewRec* __restrict__ views, int V, int L,
                                                   float fa, uint32_t flags, const float* __restrict__ pack,
                                                   float* __restrict__ dfeat, float* __restrict__ dpos,
                                                   double* __restrict__ partials) {
-    using PL = PackLayout<C>;
-    extern __shared__ double acc_lds[];     // [4 waves][V][16]
+    // single view: [256 lanes][16] FP64 per-lane sums; several views:
+    // [4 waves][V][16] per-wave sums
+    extern __shared__ double acc_lds[];
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
-    for (int j = threadIdx.x; j < 4 * V * 16; j += blockDim.x) acc_lds[j] = 0.0;
+    const int slots = SINGLE ? kBlock * 16 : 4 * V * 16;
+    for (int j = threadIdx.x; j < slots; j += blockDim.x) acc_lds[j] = 0.0;
     __syncthreads();
     const bool spatial_all = (flags & 1u) != 0;
+    const Cam c0 = load_cam(views);
+    float acc1[15];
+#pragma unroll
+    for (int t = 0; t < 15; ++t) acc1[t] = 0.f;
+    int since = 0;
 
     RangeMap m = range_map(n, (int64_t)kBlock * PPL);
     for (int64_t c = m.c0; c < m.c1; ++c) {
@@ -478,7 +611,7 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
             live[k] = i < n;
             px_[k] = py_[k] = pz_[k] = 0.f;
 #pragma unroll
-            for (int c = 0; c < C; ++c) { tau[k][c] = 0.f; dt[k][c] = 0.f; }
+            for (int ch = 0; ch < C; ++ch) { tau[k][ch] = 0.f; dt[k][ch] = 0.f; }
             dp[k][0] = dp[k][1] = dp[k][2] = 0.f;
             if (live[k]) {
                 px_[k] = xs[i];
@@ -487,77 +620,33 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
                 load_feat<C, S>(feat, i, tau[k]);
             }
         }
-        for (int v = 0; v < V; ++v) {
-            const ViewRec& c = views[v];
-            double acc[15];
-#pragma unroll
-            for (int t = 0; t < 15; ++t) acc[t] = 0.0;
+        if (SINGLE) {
             bool any = false;
 #pragma unroll
-            for (int k = 0; k < PPL; ++k) {
-                Proj p = project(c, px_[k], py_[k], pz_[k]);
-                if (!(live[k] && p.ok)) continue;
-                float gu = 0.f, gv = 0.f;
-                for (int l = 0; l < L; ++l) {
-                    int qx = 0, qy = 0;
-                    uint32_t pix = 0;
-                    bool in = layer_pixel(c, l, p.u0, p.v0, qx, qy, pix);
-                    const int lw = c.lw[l], lh = c.lh[l];
-                    float du = 0.f, dv = 0.f;
-#if ADOP_BWD_SCALAR
-                    uint64_t mk = ballot(in);
-                    if (mk == 0) continue;
-                    const int ld = __builtin_ctzll(mk);
-                    const uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pix, ld);
-                    const bool uni = ballot(in && pix != p0) == 0;
-                    if (!in) continue;
-                    if (uni) {
-                        const int ux = __builtin_amdgcn_readlane(qx, ld);
-                        const int uy = __builtin_amdgcn_readlane(qy, ld);
-                        point_layer<C>(pack, p0, ux, uy, lw, lh, p.Z, fa, spatial_all, tau[k], dt[k], du, dv);
-                    } else {
-                        point_layer<C>(pack, pix, qx, qy, lw, lh, p.Z, fa, spatial_all, tau[k], dt[k], du, dv);
-                    }
-#else
-                    if (!in) continue;
-                    point_layer<C>(pack, pix, qx, qy, lw, lh, p.Z, fa, spatial_all, tau[k], dt[k], du, dv);
-#endif
-                    const float s = 0.5f * layer_scale(l);
-                    gu = __fmaf_rn(du, s, gu);
-                    gv = __fmaf_rn(dv, s, gv);
-                }
-                if (gu == 0.f && gv == 0.f) continue;
-                any = true;
-                // chain through the projection (FP32 per-point terms)
-                const float a = p.a, b = p.b, r2 = p.r2, D = p.D;
-                const float Dp = __fmaf_rn(r2, __fmaf_rn(r2, 3.0f * c.k3, 2.0f * c.k2), c.k1);
-                const float xa = D + 2.0f * a * a * Dp + 2.0f * c.p1 * b + 6.0f * c.p2 * a;
-                const float xb = 2.0f * a * b * Dp + 2.0f * c.p1 * a + 2.0f * c.p2 * b;
-                const float yb = D + 2.0f * b * b * Dp + 6.0f * c.p1 * b + 2.0f * c.p2 * a;
-                const float gux = gu * c.fx, gvy = gv * c.fy;
-                const float ga = gux * xa + gvy * xb;
-                const float gb = gux * xb + gvy * yb;
-                const float iz = 1.0f / p.Z;
-                const float gcx = ga * iz, gcy = gb * iz, gcz = -(a * ga + b * gb) * iz;
-                dp[k][0] += c.R[0] * gcx + c.R[3] * gcy + c.R[6] * gcz;
-                dp[k][1] += c.R[1] * gcx + c.R[4] * gcy + c.R[7] * gcz;
-                dp[k][2] += c.R[2] * gcx + c.R[5] * gcy + c.R[8] * gcz;
-                const float au = gux * a + gvy * b;
-                const float r4 = r2 * r2;
-                float term[15] = {gcx, gcy, gcz,
-                                  p.Y * gcz - p.Z * gcy, p.Z * gcx - p.X * gcz, p.X * gcy - p.Y * gcx,
-                                  gu * p.xd, gv * p.yd, gu, gv, au * r2, au * r4, au * r4 * r2,
-                                  gux * 2.0f * a * b + gvy * (r2 + 2.0f * b * b),
-                                  gux * (r2 + 2.0f * a * a) + gvy * 2.0f * a * b};
-#pragma unroll
-                for (int t = 0; t < 15; ++t) acc[t] += (double)term[t];
-            }
-            if (ballot(any) != 0) {
+            for (int k = 0; k < PPL; ++k)
+                point_view<C>(c0, L, fa, spatial_all, pack, live[k], px_[k], py_[k], pz_[k], tau[k], dt[k], dp[k],
+                              acc1, any);
+            if (++since == kSuper || c + 1 == m.c1) {
+                double* slot = acc_lds + threadIdx.x * 16;
 #pragma unroll
                 for (int t = 0; t < 15; ++t) {
-                    double s = wave_sum_f64(acc[t]);
-                    if (lane == 0) acc_lds[(wave * V + v) * 16 + t] += s;
+                    slot[t] += (double)acc1[t];
+                    acc1[t] = 0.f;
                 }
+                since = 0;
+            }
+        } else {
+            for (int v = 0; v < V; ++v) {
+                const Cam cv = load_cam(views + v);
+                float acc[15];
+#pragma unroll
+                for (int t = 0; t < 15; ++t) acc[t] = 0.f;
+                bool any = false;
+#pragma unroll
+                for (int k = 0; k < PPL; ++k)
+                    point_view<C>(cv, L, fa, spatial_all, pack, live[k], px_[k], py_[k], pz_[k], tau[k], dt[k],
+                                  dp[k], acc, any);
+                reduce_terms(acc, any, acc_lds + (wave * V + v) * 16, lane);
             }
         }
 #pragma unroll
@@ -571,10 +660,26 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
         }
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < V * 16; j += blockDim.x) {
+    if (SINGLE) {
+        // fixed-order sum of the 256 lanes' FP64 partials: 16 threads per
+        // term each sum 16 lanes, then one thread sums the 16 results
+        __shared__ double red[16][16];
+        const int t = threadIdx.x & 15, part = threadIdx.x >> 4;
         double s = 0.0;
-        for (int w = 0; w < 4; ++w) s += acc_lds[w * V * 16 + j];
-        partials[(uint64_t)blockIdx.x * V * 16 + j] = s;
+        for (int j = 0; j < 16; ++j) s += acc_lds[(part * 16 + j) * 16 + t];
+        red[part][t] = s;
+        __syncthreads();
+        if (threadIdx.x < 16) {
+            double r = 0.0;
+            for (int j = 0; j < 16; ++j) r += red[j][threadIdx.x];
+            partials[(uint64_t)blockIdx.x * 16 + threadIdx.x] = r;
+        }
+    } else {
+        for (int j = threadIdx.x; j < V * 16; j += blockDim.x) {
+            double s = 0.0;
+            for (int w = 0; w < 4; ++w) s += acc_lds[w * V * 16 + j];
+            partials[(uint64_t)blockIdx.x * V * 16 + j] = s;
+        }
     }
 }
 
@@ -644,24 +749,30 @@ static inline unsigned persistent_grid(int64_t n, int64_t chunk, int cus, int pe
     return (unsigned)g;
 }
 
+template <int C, typename S, bool SINGLE>
+static void forward_points(const FwdArgs& a, hipStream_t st) {
+    static const int occ_depth = resident(k_depth<SINGLE>, 0);
+    static const int occ_accum = resident(k_accum<C, S, SINGLE>, 0);
+    unsigned gd = persistent_grid(a.n, kBlock, a.cus, occ_depth, 1 << 20);
+    a.timer.mark(kKDepth, 0, st);
+    k_depth<SINGLE><<<gd, kBlock, 0, st>>>(a.x, a.y, a.z, a.orig, a.n, a.views, a.V, a.L, a.keys);
+    a.timer.mark(kKDepth, 1, st);
+    unsigned ga = persistent_grid(a.n, kBlock, a.cus, occ_accum, 1 << 20);
+    a.timer.mark(kKAccum, 0, st);
+    k_accum<C, S, SINGLE><<<ga, kBlock, 0, st>>>(a.x, a.y, a.z, a.feat, a.n, a.views, a.V, a.L, a.fa,
+                                                  reinterpret_cast<const uint32_t*>(a.keys), a.sums, a.counts);
+    a.timer.mark(kKAccum, 1, st);
+}
+
 template <int C, typename S>
 static hipError_t forward_impl(const FwdArgs& a, hipStream_t st) {
-    static const int occ_depth = resident(k_depth, 0);
-    static const int occ_accum = resident(k_accum<C, S>, 0);
     unsigned gp = grid_for(a.pixels, 256 * 4, a.cus * 8);
     a.timer.mark(kKClear, 0, st);
     k_clear<<<gp, 256, 0, st>>>(a.keys, a.counts, a.sums, a.pixels, a.pixels * C);
     a.timer.mark(kKClear, 1, st);
     if (a.n > 0) {
-        unsigned gd = persistent_grid(a.n, kBlock, a.cus, occ_depth, 1 << 20);
-        a.timer.mark(kKDepth, 0, st);
-        k_depth<<<gd, kBlock, 0, st>>>(a.x, a.y, a.z, a.orig, a.n, a.views, a.V, a.L, a.keys);
-        a.timer.mark(kKDepth, 1, st);
-        unsigned ga = persistent_grid(a.n, kBlock, a.cus, occ_accum, 1 << 20);
-        a.timer.mark(kKAccum, 0, st);
-        k_accum<C, S><<<ga, kBlock, 0, st>>>(a.x, a.y, a.z, a.feat, a.n, a.views, a.V, a.L, a.fa,
-                                              reinterpret_cast<const uint32_t*>(a.keys), a.sums, a.counts);
-        a.timer.mark(kKAccum, 1, st);
+        if (a.V == 1) forward_points<C, S, true>(a, st);
+        else forward_points<C, S, false>(a, st);
     }
     dim3 gn((unsigned)std::min<int64_t>((a.max_layer_pixels + 255) / 256, 1024), (unsigned)(a.V * a.L));
     a.timer.mark(kKNormalize, 0, st);
@@ -670,21 +781,28 @@ static hipError_t forward_impl(const FwdArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <int C, typename S, bool SINGLE>
+static unsigned backward_points(const BwdArgs& a, hipStream_t st) {
+    constexpr int PPL = C <= 4 ? ADOP_PPL4 : 2;
+    const size_t lds = SINGLE ? (size_t)kBlock * 16 * sizeof(double) : (size_t)4 * a.V * 16 * sizeof(double);
+    static const int occ = resident(k_backward<C, S, PPL, SINGLE>,
+                                    SINGLE ? lds : (size_t)4 * kMaxViewsBwd * 16 * sizeof(double));
+    unsigned g = persistent_grid(a.n, (int64_t)kBlock * PPL, a.cus, occ, a.groups);
+    a.timer.mark(kKBackward, 0, st);
+    k_backward<C, S, PPL, SINGLE><<<g, kBlock, lds, st>>>(a.x, a.y, a.z, a.feat, a.n, a.views, a.V, a.L, a.fa,
+                                                          a.flags, a.pack, a.dfeat, a.dpos, a.partials);
+    a.timer.mark(kKBackward, 1, st);
+    return g;
+}
+
 template <int C, typename S>
 static hipError_t backward_impl(const BwdArgs& a, hipStream_t st) {
-    constexpr int PPL = C <= 4 ? ADOP_PPL4 : 2;
-    size_t lds = (size_t)4 * a.V * 16 * sizeof(double);
     dim3 gn((unsigned)std::min<int64_t>((a.max_layer_pixels + 255) / 256, 1024), (unsigned)(a.V * a.L));
     a.timer.mark(kKPack, 0, st);
     k_pack<C><<<gn, 256, 0, st>>>(a.views, a.L, a.keys, a.counts, a.images, a.grad, a.pack,
                                  make_bg(a.background, C));
     a.timer.mark(kKPack, 1, st);
-    static const int occ = resident(k_backward<C, S, PPL>, (size_t)4 * kMaxViewsBwd * 16 * sizeof(double));
-    unsigned g = persistent_grid(a.n, (int64_t)kBlock * PPL, a.cus, occ, a.groups);
-    a.timer.mark(kKBackward, 0, st);
-    k_backward<C, S, PPL><<<g, kBlock, lds, st>>>(a.x, a.y, a.z, a.feat, a.n, a.views, a.V, a.L, a.fa,
-                                                  a.flags, a.pack, a.dfeat, a.dpos, a.partials);
-    a.timer.mark(kKBackward, 1, st);
+    unsigned g = a.V == 1 ? backward_points<C, S, true>(a, st) : backward_points<C, S, false>(a, st);
     a.timer.mark(kKReduce, 0, st);
     k_reduce<<<a.V, 256, 0, st>>>(a.partials, (int)g, a.V, a.dpose, a.dintr);
     a.timer.mark(kKReduce, 1, st);
@@ -714,6 +832,15 @@ int backward_points_per_group(int C) { return kBlock * (C <= 4 ? ADOP_PPL4 : 2);
         default: return hipErrorInvalidValue;       \
     }
 
+#ifdef ADOP_TUNE_C4_F32_ONLY
+// tuning builds: only 4 channels, FP32 storage
+hipError_t launch_forward(const FwdArgs& a, hipStream_t st) {
+    return (a.C == 4 && a.dtype == 0) ? forward_impl<4, F32>(a, st) : hipErrorInvalidValue;
+}
+hipError_t launch_backward(const BwdArgs& a, hipStream_t st) {
+    return (a.C == 4 && a.dtype == 0) ? backward_impl<4, F32>(a, st) : hipErrorInvalidValue;
+}
+#else
 hipError_t launch_forward(const FwdArgs& a, hipStream_t st) {
     switch (a.dtype) {
         case 0: ADOP_DISPATCH_C(forward_impl, F32, a, st)
@@ -731,5 +858,6 @@ hipError_t launch_backward(const BwdArgs& a, hipStream_t st) {
         default: return hipErrorInvalidValue;
     }
 }
+#endif
 
 }  // namespace adop
