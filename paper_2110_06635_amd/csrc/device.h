@@ -237,6 +237,18 @@ template <> __device__ __forceinline__ float widen<F16>(uint16_t v) {
     return (float)h;
 }
 
+// Streaming accesses to the point arrays (each element is touched once per
+// pass) are non-temporal, so they do not push the gathered pixel data (keys,
+// per-pixel records) out of the caches.
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef float vf2 __attribute__((ext_vector_type(2)));
+typedef unsigned int vu4 __attribute__((ext_vector_type(4)));
+typedef unsigned int vu2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float ld_nt(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ int32_t ld_nt(const int32_t* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void st_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
+
 // Load the C features of point i (row-major [n][C]) widened to FP32.
 template <int C, typename S>
 __device__ __forceinline__ void load_feat(const void* feat, int64_t i, float (&f)[C]) {
@@ -244,17 +256,27 @@ __device__ __forceinline__ void load_feat(const void* feat, int64_t i, float (&f
     const T* p = reinterpret_cast<const T*>(feat) + i * C;
     constexpr int bytes = C * S::bytes;
     if constexpr (bytes % 16 == 0) {
-        const uint4* q = reinterpret_cast<const uint4*>(p);
+        const vu4* q = reinterpret_cast<const vu4*>(p);
         T tmp[C];
 #pragma unroll
-        for (int k = 0; k < bytes / 16; ++k) reinterpret_cast<uint4*>(tmp)[k] = q[k];
+        for (int k = 0; k < bytes / 16; ++k) {
+            vu4 v = __builtin_nontemporal_load(q + k);
+            reinterpret_cast<uint32_t*>(tmp)[4 * k] = v.x;
+            reinterpret_cast<uint32_t*>(tmp)[4 * k + 1] = v.y;
+            reinterpret_cast<uint32_t*>(tmp)[4 * k + 2] = v.z;
+            reinterpret_cast<uint32_t*>(tmp)[4 * k + 3] = v.w;
+        }
 #pragma unroll
         for (int c = 0; c < C; ++c) f[c] = widen<S>(tmp[c]);
     } else if constexpr (bytes % 8 == 0) {
-        const uint2* q = reinterpret_cast<const uint2*>(p);
+        const vu2* q = reinterpret_cast<const vu2*>(p);
         T tmp[C];
 #pragma unroll
-        for (int k = 0; k < bytes / 8; ++k) reinterpret_cast<uint2*>(tmp)[k] = q[k];
+        for (int k = 0; k < bytes / 8; ++k) {
+            vu2 v = __builtin_nontemporal_load(q + k);
+            reinterpret_cast<uint32_t*>(tmp)[2 * k] = v.x;
+            reinterpret_cast<uint32_t*>(tmp)[2 * k + 1] = v.y;
+        }
 #pragma unroll
         for (int c = 0; c < C; ++c) f[c] = widen<S>(tmp[c]);
     } else {
@@ -268,14 +290,19 @@ __device__ __forceinline__ void store_f32_row(float* out, int64_t i, const float
     float* p = out + i * C;
     if constexpr (C % 4 == 0) {
 #pragma unroll
-        for (int k = 0; k < C / 4; ++k)
-            reinterpret_cast<float4*>(p)[k] = make_float4(f[4 * k], f[4 * k + 1], f[4 * k + 2], f[4 * k + 3]);
+        for (int k = 0; k < C / 4; ++k) {
+            vf4 v = {f[4 * k], f[4 * k + 1], f[4 * k + 2], f[4 * k + 3]};
+            __builtin_nontemporal_store(v, reinterpret_cast<vf4*>(p) + k);
+        }
     } else if constexpr (C % 2 == 0) {
 #pragma unroll
-        for (int k = 0; k < C / 2; ++k) reinterpret_cast<float2*>(p)[k] = make_float2(f[2 * k], f[2 * k + 1]);
+        for (int k = 0; k < C / 2; ++k) {
+            vf2 v = {f[2 * k], f[2 * k + 1]};
+            __builtin_nontemporal_store(v, reinterpret_cast<vf2*>(p) + k);
+        }
     } else {
 #pragma unroll
-        for (int c = 0; c < C; ++c) p[c] = f[c];
+        for (int c = 0; c < C; ++c) st_nt(p + c, f[c]);
     }
 }
 

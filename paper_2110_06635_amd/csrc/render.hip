@@ -196,17 +196,26 @@ __global__ void __launch_bounds__(256) k_depth(const float* __restrict__ xs, con
 #endif
     const Cam c0 = load_cam(views);
     RangeMap m = range_map(n, kBlock);
-    for (int64_t c = m.c0; c < m.c1; ++c) {
+    // the next chunk's points are loaded while the current one is processed
+    float nx = 0.f, ny = 0.f, nz = 0.f;
+    uint32_t noi = 0;
+    bool nlive = false;
+    auto fetch = [&](int64_t c) {
         int64_t i = c * kBlock + threadIdx.x;
-        bool live = i < n;
-        float x = 0.f, y = 0.f, z = 0.f;
-        uint32_t oi = 0;
-        if (live) {
-            x = xs[i];
-            y = ys[i];
-            z = zs[i];
-            oi = (uint32_t)orig[i];
+        nlive = i < n;
+        if (nlive) {
+            nx = ld_nt(xs + i);
+            ny = ld_nt(ys + i);
+            nz = ld_nt(zs + i);
+            noi = (uint32_t)ld_nt(orig + i);
         }
+    };
+    if (m.c0 < m.c1) fetch(m.c0);
+    for (int64_t c = m.c0; c < m.c1; ++c) {
+        const bool live = nlive;
+        const float x = nx, y = ny, z = nz;
+        const uint32_t oi = noi;
+        if (c + 1 < m.c1) fetch(c + 1);
         if (SINGLE) {
             depth_point(c0, L, live, x, y, z, oi, t, keys);
         } else {
@@ -338,19 +347,29 @@ __global__ void __launch_bounds__(256) k_accum(const float* __restrict__ xs, con
     __syncthreads();
     const Cam c0 = load_cam(views);
     RangeMap m = range_map(n, kBlock);
-    for (int64_t c = m.c0; c < m.c1; ++c) {
+    // the next chunk's points are loaded while the current one is processed
+    float nx = 0.f, ny = 0.f, nz = 0.f, nf[C];
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch) nf[ch] = 0.f;
+    bool nlive = false;
+    auto fetch = [&](int64_t c) {
         int64_t i = c * kBlock + threadIdx.x;
-        bool live = i < n;
-        float x = 0.f, y = 0.f, z = 0.f;
+        nlive = i < n;
+        if (nlive) {
+            nx = ld_nt(xs + i);
+            ny = ld_nt(ys + i);
+            nz = ld_nt(zs + i);
+            load_feat<C, S>(feat, i, nf);
+        }
+    };
+    if (m.c0 < m.c1) fetch(m.c0);
+    for (int64_t c = m.c0; c < m.c1; ++c) {
+        const bool live = nlive;
+        const float x = nx, y = ny, z = nz;
         float f[C];
 #pragma unroll
-        for (int ch = 0; ch < C; ++ch) f[ch] = 0.f;
-        if (live) {
-            x = xs[i];
-            y = ys[i];
-            z = zs[i];
-            load_feat<C, S>(feat, i, f);
-        }
+        for (int ch = 0; ch < C; ++ch) f[ch] = nf[ch];
+        if (c + 1 < m.c1) fetch(c + 1);
         if (SINGLE) {
             accum_point<C>(c0, L, fa, live, x, y, z, f, keys32, t, sums, counts);
         } else {
@@ -614,9 +633,9 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
             for (int ch = 0; ch < C; ++ch) { tau[k][ch] = 0.f; dt[k][ch] = 0.f; }
             dp[k][0] = dp[k][1] = dp[k][2] = 0.f;
             if (live[k]) {
-                px_[k] = xs[i];
-                py_[k] = ys[i];
-                pz_[k] = zs[i];
+                px_[k] = ld_nt(xs + i);
+                py_[k] = ld_nt(ys + i);
+                pz_[k] = ld_nt(zs + i);
                 load_feat<C, S>(feat, i, tau[k]);
             }
         }
@@ -654,9 +673,9 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
             if (!live[k]) continue;
             int64_t i = wbase + (int64_t)k * kWave + lane;
             store_f32_row<C>(dfeat, i, dt[k]);
-            dpos[i] = dp[k][0];
-            dpos[n + i] = dp[k][1];
-            dpos[2 * n + i] = dp[k][2];
+            st_nt(dpos + i, dp[k][0]);
+            st_nt(dpos + n + i, dp[k][1]);
+            st_nt(dpos + 2 * n + i, dp[k][2]);
         }
     }
     __syncthreads();
