@@ -108,33 +108,30 @@ __device__ __forceinline__ Proj project(const CamT& c, float x, float y, float z
 }
 
 // Pixel of layer l (Eq. round + Eq. boundscheck): rint(u0 * 2^-l), in
-// [0,w_l) x [0,h_l).  Returns the frame pixel index in *pix.
-template <typename CamT>
-__device__ __forceinline__ bool layer_pixel(const CamT& c, int l, float u0, float v0,
-                                            int& px, int& py, uint32_t& pix) {
-    float s = layer_scale(l);
-    float fx = __builtin_rintf(__fmul_rn(u0, s));
-    float fy = __builtin_rintf(__fmul_rn(v0, s));
-    int lw = c.lw[l], lh = c.lh[l];
-    bool in = fx >= 0.0f && fx < (float)lw && fy >= 0.0f && fy < (float)lh;
-    px = in ? (int)fx : 0;
-    py = in ? (int)fy : 0;
-    pix = c.base[l] + (uint32_t)py * (uint32_t)lw + (uint32_t)px;
-    return in;
-}
-
-// The same as layer_pixel with the layer size and first pixel given (for
-// loops over layers that are not unrolled: w_l = w >> l, h_l = h >> l).
-__device__ __forceinline__ bool layer_pixel_at(int l, int lw, int lh, uint32_t base, float u0, float v0,
+// [0,w_l) x [0,h_l), for a point whose projection is valid (ok).  The
+// rounded coordinate is an integer-valued float; clamped into [-1, 2^24] it
+// converts exactly, and the float range test becomes one unsigned compare
+// (-0 maps to 0 and stays inside, as the float test keeps it).  u0, v0 are
+// finite whenever ok holds.  Lanes outside get px = py = 0, so *pix is the
+// layer's first pixel: always a valid address to load from.
+__device__ __forceinline__ bool layer_pixel_at(bool ok, int l, int lw, int lh, uint32_t base, float u0, float v0,
                                                int& px, int& py, uint32_t& pix) {
     float s = layer_scale(l);
     float fx = __builtin_rintf(__fmul_rn(u0, s));
     float fy = __builtin_rintf(__fmul_rn(v0, s));
-    bool in = fx >= 0.0f && fx < (float)lw && fy >= 0.0f && fy < (float)lh;
-    px = in ? (int)fx : 0;
-    py = in ? (int)fy : 0;
+    int ix = (int)__builtin_amdgcn_fmed3f(fx, -1.0f, 16777216.0f);
+    int iy = (int)__builtin_amdgcn_fmed3f(fy, -1.0f, 16777216.0f);
+    bool in = ok & ((uint32_t)ix < (uint32_t)lw) & ((uint32_t)iy < (uint32_t)lh);
+    px = in ? ix : 0;
+    py = in ? iy : 0;
     pix = base + (uint32_t)py * (uint32_t)lw + (uint32_t)px;
     return in;
+}
+
+template <typename CamT>
+__device__ __forceinline__ bool layer_pixel(const CamT& c, bool ok, int l, float u0, float v0,
+                                            int& px, int& py, uint32_t& pix) {
+    return layer_pixel_at(ok, l, c.lw[l], c.lh[l], c.base[l], u0, v0, px, py, pix);
 }
 
 // ----------------------------------------------------------------------------
@@ -160,6 +157,24 @@ __device__ __forceinline__ float wave_sum(float v) {
     v += __uint_as_float(dpp_u32<0x142, 0xa, false>(0u, __float_as_uint(v)));
     v += __uint_as_float(dpp_u32<0x143, 0xc, false>(0u, __float_as_uint(v)));
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+// wave_sum of N values at once: the DPP steps of the N sums are interleaved,
+// so no step waits on the one before it in the same chain.
+template <int N>
+__device__ __forceinline__ void wave_sum_n(float (&v)[N]) {
+#define ADOP_SUM_STEP(CTRL, RM, BC)                                                              \
+    _Pragma("unroll") for (int i = 0; i < N; ++i)                                               \
+        v[i] += __uint_as_float(dpp_u32<CTRL, RM, BC>(0u, __float_as_uint(v[i])));
+    ADOP_SUM_STEP(0x111, 0xf, true)
+    ADOP_SUM_STEP(0x112, 0xf, true)
+    ADOP_SUM_STEP(0x114, 0xf, true)
+    ADOP_SUM_STEP(0x118, 0xf, true)
+    ADOP_SUM_STEP(0x142, 0xa, false)
+    ADOP_SUM_STEP(0x143, 0xc, false)
+#undef ADOP_SUM_STEP
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[i]), 63));
 }
 
 template <int CTRL, int ROWMASK, bool BOUND>

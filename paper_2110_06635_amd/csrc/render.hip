@@ -54,6 +54,28 @@ namespace adop {
 #ifndef ADOP_ACC_TABLE
 #define ADOP_ACC_TABLE 1
 #endif
+// ADOP_BWD_HOIST 1: the backward gathers every layer's min_z before the
+// per-layer neighbour work (one round trip instead of one per layer)
+#ifndef ADOP_BWD_HOIST
+#define ADOP_BWD_HOIST 1
+#endif
+// minimum waves per SIMD the point kernels are compiled for (bounds their
+// register use); 0 leaves the choice to the compiler
+#ifndef ADOP_DEPTH_WPE
+#define ADOP_DEPTH_WPE 0
+#endif
+#ifndef ADOP_ACCUM_WPE
+#define ADOP_ACCUM_WPE 0
+#endif
+#ifndef ADOP_BWD_WPE
+#define ADOP_BWD_WPE 0
+#endif
+#define ADOP_WPE_ATTR(n) __attribute__((amdgpu_waves_per_eu((n) > 0 ? (n) : 1)))
+// ADOP_ACC_WCACHE 1: per-wave register cache of 64 pixel sums in front of
+// the workgroup table
+#ifndef ADOP_ACC_WCACHE
+#define ADOP_ACC_WCACHE 1
+#endif
 #ifndef ADOP_PPL4
 #define ADOP_PPL4 4
 #endif
@@ -145,7 +167,7 @@ __device__ __forceinline__ void depth_point(const Cam& c, int L, bool live, floa
         if (l >= L) break;
         int px = 0, py = 0;
         uint32_t pix = 0;
-        bool in = ok && layer_pixel(c, l, p.u0, p.v0, px, py, pix);
+        bool in = layer_pixel(c, ok, l, p.u0, p.v0, px, py, pix);
         depth_update(in, pix, key, *t, keys);
     }
 #else
@@ -159,8 +181,8 @@ __device__ __forceinline__ void depth_point(const Cam& c, int L, bool live, floa
         cur[l] = 0;
         if (l < L) {
             int px = 0, py = 0;
-            in[l] = ok && layer_pixel(c, l, p.u0, p.v0, px, py, pix[l]);
-            if (in[l]) cur[l] = load_relaxed_u64(keys + pix[l]);
+            in[l] = layer_pixel(c, ok, l, p.u0, p.v0, px, py, pix[l]);
+            cur[l] = load_relaxed_u64(keys + pix[l]);   // pix is valid for every lane
         }
     }
 #pragma unroll
@@ -182,7 +204,7 @@ __device__ __forceinline__ void depth_point(const Cam& c, int L, bool live, floa
 }
 
 template <bool SINGLE>
-__global__ void __launch_bounds__(256) k_depth(const float* __restrict__ xs, const float* __restrict__ ys,
+__global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_DEPTH_WPE) k_depth(const float* __restrict__ xs, const float* __restrict__ ys,
                                                const float* __restrict__ zs, const int32_t* __restrict__ orig,
                                                int64_t n, const ViewRec* __restrict__ views, int V, int L,
                                                uint64_t* __restrict__ keys) {
@@ -257,12 +279,64 @@ __device__ __forceinline__ void table_add(AccTable<C>& t, float* __restrict__ su
     __hip_atomic_fetch_add(&t.cnt[slot], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Per-wave cache of 64 pixel sums, one slot per lane (direct mapped by a
+// hash of the pixel): a wave's group totals land in a register of the slot's
+// lane; a slot taken by another pixel is first written to the workgroup
+// table.  Consecutive Morton-ordered points hit the same pixels again, so
+// most group totals never touch LDS.
+template <int C> struct WaveCache {
+    uint32_t key;
+    float sum[C];
+    int32_t cnt;
+};
+
+template <int C>
+__device__ __forceinline__ void wcache_init(WaveCache<C>& w) {
+    w.key = kEmptySlot;
+#pragma unroll
+    for (int c = 0; c < C; ++c) w.sum[c] = 0.f;
+    w.cnt = 0;
+}
+
+// s and k are wave-uniform; every lane calls this.
+template <int C>
+__device__ __forceinline__ void wcache_add(WaveCache<C>& w, uint32_t p0, const float (&s)[C], int32_t k,
+                                           AccTable<C>& t, float* __restrict__ sums, int32_t* __restrict__ counts) {
+    const int slot = (int)((p0 * 2654435761u) >> 26);
+    const uint32_t ck = (uint32_t)__builtin_amdgcn_readlane((int)w.key, slot);
+    const bool me = lane_id() == slot;
+    if (ck != p0) {
+        if (me) {
+            if (ck != kEmptySlot) table_add<C>(t, sums, counts, ck, w.sum, w.cnt);
+            w.key = p0;
+#pragma unroll
+            for (int c = 0; c < C; ++c) w.sum[c] = s[c];
+            w.cnt = k;
+        }
+    } else if (me) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) w.sum[c] += s[c];
+        w.cnt += k;
+    }
+}
+
+template <int C>
+__device__ __forceinline__ void wcache_flush(WaveCache<C>& w, AccTable<C>& t, float* __restrict__ sums,
+                                             int32_t* __restrict__ counts) {
+    if (w.key != kEmptySlot) table_add<C>(t, sums, counts, w.key, w.sum, w.cnt);
+    wcache_init<C>(w);
+}
+
 // Lanes whose point passes are grouped by pixel: the first remaining lane's
 // pixel, the ballot of the lanes sharing it, DPP sums; groups smaller than
 // kMinGroup (and lanes left after kMaxGroups) add individually.
 template <int C>
 __device__ __forceinline__ void accum_update(bool pass, uint32_t pix, const float (&f)[C], AccTable<C>& t,
-                                             float* __restrict__ sums, int32_t* __restrict__ counts) {
+                                             float* __restrict__ sums, int32_t* __restrict__ counts
+#if ADOP_ACC_WCACHE
+                                             , WaveCache<C>& w
+#endif
+                                             ) {
     uint64_t rem = ballot(pass);
     if (rem == 0) return;
     const int lane = lane_id();
@@ -276,8 +350,13 @@ __device__ __forceinline__ void accum_update(bool pass, uint32_t pix, const floa
         bool mine = (mm >> lane) & 1;
         float s[C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) s[c] = wave_sum(mine ? f[c] : 0.0f);
+        for (int c = 0; c < C; ++c) s[c] = mine ? f[c] : 0.0f;
+        wave_sum_n<C>(s);
+#if ADOP_ACC_WCACHE
+        wcache_add<C>(w, p0, s, k, t, sums, counts);
+#else
         if (lane == leader) table_add<C>(t, sums, counts, p0, s, k);
+#endif
         rem &= ~mm;
     }
     if ((rem >> lane) & 1) table_add<C>(t, sums, counts, pix, f, 1);
@@ -307,9 +386,16 @@ __device__ __forceinline__ void acc_table_flush(AccTable<C>& t, float* __restric
 }
 
 template <int C>
+#if ADOP_ACC_WCACHE
+#define ADOP_WC_PARAM , WaveCache<C>& w
+#define ADOP_WC_ARG , w
+#else
+#define ADOP_WC_PARAM
+#define ADOP_WC_ARG
+#endif
 __device__ __forceinline__ void accum_point(const Cam& c, int L, float fa, bool live, float x, float y, float z,
                                             const float (&f)[C], const uint32_t* __restrict__ keys32, AccTable<C>& t,
-                                            float* __restrict__ sums, int32_t* __restrict__ counts) {
+                                            float* __restrict__ sums, int32_t* __restrict__ counts ADOP_WC_PARAM) {
     Proj p = project(c, x, y, z);
     bool ok = live && p.ok;
     // all layers' front depths are gathered before any update, so the
@@ -324,20 +410,20 @@ __device__ __forceinline__ void accum_point(const Cam& c, int L, float fa, bool 
         mz[l] = 0.f;
         if (l < L) {
             int px = 0, py = 0;
-            in[l] = ok && layer_pixel(c, l, p.u0, p.v0, px, py, pix[l]);
-            if (in[l]) mz[l] = __uint_as_float(keys32[2 * (uint64_t)pix[l] + 1]);
+            in[l] = layer_pixel(c, ok, l, p.u0, p.v0, px, py, pix[l]);
+            mz[l] = __uint_as_float(keys32[2 * (uint64_t)pix[l] + 1]);   // pix is valid for every lane
         }
     }
 #pragma unroll
     for (int l = 0; l < kMaxLayers; ++l) {
         if (l >= L) break;
         bool pass = in[l] && p.Z <= __fmul_rn(mz[l], fa);
-        accum_update<C>(pass, pix[l], f, t, sums, counts);
+        accum_update<C>(pass, pix[l], f, t, sums, counts ADOP_WC_ARG);
     }
 }
 
 template <int C, typename S, bool SINGLE>
-__global__ void __launch_bounds__(256) k_accum(const float* __restrict__ xs, const float* __restrict__ ys,
+__global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_ACCUM_WPE) k_accum(const float* __restrict__ xs, const float* __restrict__ ys,
                                                const float* __restrict__ zs, const void* __restrict__ feat,
                                                int64_t n, const ViewRec* __restrict__ views, int V, int L,
                                                float fa, const uint32_t* __restrict__ keys32,
@@ -345,6 +431,10 @@ __global__ void __launch_bounds__(256) k_accum(const float* __restrict__ xs, con
     __shared__ AccTable<C> t;
     acc_table_clear<C>(t);
     __syncthreads();
+#if ADOP_ACC_WCACHE
+    WaveCache<C> w;
+    wcache_init<C>(w);
+#endif
     const Cam c0 = load_cam(views);
     RangeMap m = range_map(n, kBlock);
     // the next chunk's points are loaded while the current one is processed
@@ -371,12 +461,15 @@ __global__ void __launch_bounds__(256) k_accum(const float* __restrict__ xs, con
         for (int ch = 0; ch < C; ++ch) f[ch] = nf[ch];
         if (c + 1 < m.c1) fetch(c + 1);
         if (SINGLE) {
-            accum_point<C>(c0, L, fa, live, x, y, z, f, keys32, t, sums, counts);
+            accum_point<C>(c0, L, fa, live, x, y, z, f, keys32, t, sums, counts ADOP_WC_ARG);
         } else {
             for (int v = 0; v < V; ++v)
-                accum_point<C>(load_cam(views + v), L, fa, live, x, y, z, f, keys32, t, sums, counts);
+                accum_point<C>(load_cam(views + v), L, fa, live, x, y, z, f, keys32, t, sums, counts ADOP_WC_ARG);
         }
     }
+#if ADOP_ACC_WCACHE
+    wcache_flush<C>(w, t, sums, counts);
+#endif
     __syncthreads();
     acc_table_flush<C>(t, sums, counts);
 }
@@ -530,18 +623,55 @@ __device__ __forceinline__ void point_view(const Cam& c, int L, float fa, bool s
     Proj p = project(c, x, y, z);
     if (!(live && p.ok)) return;
     float gu = 0.f, gv = 0.f;
+#if ADOP_BWD_HOIST
+    // bit l of work: the layer needs the neighbour records; bit l of seen:
+    // the point is in the layer's blend set
+    uint32_t work = 0, seen = 0;
+    {
+        float mz[kMaxLayers];
+        bool in[kMaxLayers];
+#pragma unroll
+        for (int l = 0; l < kMaxLayers; ++l) {
+            mz[l] = 0.f;
+            in[l] = false;
+            if (l < L) {
+                int qx = 0, qy = 0;
+                uint32_t pix = 0;
+                in[l] = layer_pixel(c, true, l, p.u0, p.v0, qx, qy, pix);
+                mz[l] = pack[(uint64_t)pix * PL::stride + PL::minz];   // pix is valid for every lane
+            }
+        }
+#pragma unroll
+        for (int l = 0; l < kMaxLayers; ++l) {
+            const bool vis = in[l] && p.Z <= __fmul_rn(mz[l], fa);
+            seen |= (uint32_t)vis << l;
+            work |= (uint32_t)(vis || (spatial_all && in[l])) << l;
+        }
+    }
+    uint32_t base = c.base[0];
+#pragma unroll 1
+    for (int l = 0; l < L; ++l) {
+        const int lw = c.w >> l, lh = c.h >> l;
+        const uint32_t lbase = base;
+        base += (uint32_t)lw * (uint32_t)lh;
+        if (!((work >> l) & 1u)) continue;
+        int qx = 0, qy = 0;
+        uint32_t pix = 0;
+        layer_pixel_at(true, l, lw, lh, lbase, p.u0, p.v0, qx, qy, pix);
+        const bool vis = (seen >> l) & 1u;
+#else
     uint32_t base = c.base[0];
 #pragma unroll 1
     for (int l = 0; l < L; ++l) {
         const int lw = c.w >> l, lh = c.h >> l;
         int qx = 0, qy = 0;
         uint32_t pix = 0;
-        const bool in = layer_pixel_at(l, lw, lh, base, p.u0, p.v0, qx, qy, pix);
+        const bool in = layer_pixel_at(true, l, lw, lh, base, p.u0, p.v0, qx, qy, pix);
         base += (uint32_t)lw * (uint32_t)lh;
-        float mz = 0.f;
-        if (in) mz = pack[(uint64_t)pix * PL::stride + PL::minz];
+        const float mz = pack[(uint64_t)pix * PL::stride + PL::minz];   // pix is valid for every lane
         const bool vis = in && p.Z <= __fmul_rn(mz, fa);
         if (!(vis || (spatial_all && in))) continue;
+#endif
         float du = 0.f, dv = 0.f;
         layer_work<C>(pack, pix, qx, qy, lw, lh, p.Z, fa, vis, tau, dt, du, dv);
         const float s = 0.5f * layer_scale(l);
@@ -597,7 +727,7 @@ __device__ __forceinline__ void reduce_terms(const float (&acc)[15], bool any, d
 constexpr int kSuper = 4;   // chunks a lane sums in FP32 before widening (single view)
 
 template <int C, typename S, int PPL, bool SINGLE>
-__global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, const float* __restrict__ ys,
+__global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_BWD_WPE) k_backward(const float* __restrict__ xs, const float* __restrict__ ys,
                                                   const float* __restrict__ zs, const void* __restrict__ feat,
                                                   int64_t n, const ViewRec* __restrict__ views, int V, int L,
                                                   float fa, uint32_t flags, const float* __restrict__ pack,
