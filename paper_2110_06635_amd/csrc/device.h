@@ -324,10 +324,14 @@ __device__ __forceinline__ void store_f32_row(float* out, int64_t i, const float
 // Per-pixel record the backward pass gathers: upstream gradient G (C floats),
 // gdot = <G, I> (or <G, background> for an empty pixel), the front depth
 // min_z as float bits, and the blend count n.
+// Per-pixel record of the backward pass: G (C floats), <G, I> (<G, b> for an
+// empty pixel), min_z, (1+alpha) min_z and the count as a float; an empty
+// pixel has min_z = (1+alpha) min_z = +inf, so the case tests need no
+// separate emptiness check.
 template <int C> struct PackLayout {
-    static constexpr int used = C + 3;
+    static constexpr int used = C + 4;
     static constexpr int stride = (used + 3) / 4 * 4;   // floats, multiple of 4
-    static constexpr int gdot = C, minz = C + 1, count = C + 2;
+    static constexpr int gdot = C, minz = C + 1, behind = C + 2, count = C + 3;
 };
 
 // Range mapping of the point kernels: the grid is persistent (a multiple of

@@ -511,7 +511,7 @@ __global__ void __launch_bounds__(256) k_pack(const ViewRec* __restrict__ views,
                                               const int32_t* __restrict__ counts,
                                               const float* __restrict__ images,
                                               const float* __restrict__ grad,
-                                              float* __restrict__ pack, Background bg) {
+                                              float* __restrict__ pack, float fa, Background bg) {
     using PL = PackLayout<C>;
     int vl = blockIdx.y;
     int v = vl / L, l = vl - (vl / L) * L;
@@ -533,9 +533,12 @@ __global__ void __launch_bounds__(256) k_pack(const ViewRec* __restrict__ views,
             rec[ch] = g;
             gdot = __fmaf_rn(g, I, gdot);
         }
+        const float inf = __builtin_inff();
+        const float mzf = __uint_as_float(minz);
         rec[PL::gdot] = gdot;
-        rec[PL::minz] = __uint_as_float(minz);
-        rec[PL::count] = __int_as_float(k);
+        rec[PL::minz] = k > 0 ? mzf : inf;
+        rec[PL::behind] = k > 0 ? __fmul_rn(mzf, fa) : inf;
+        rec[PL::count] = (float)k;
 #pragma unroll
         for (int q = PL::used; q < PL::stride; ++q) rec[q] = 0.f;
         float4* dst = reinterpret_cast<float4*>(pack + p * PL::stride);
@@ -566,19 +569,16 @@ __device__ __forceinline__ void load_rec(const float* __restrict__ pack, uint64_
 }
 
 template <int C>
-__device__ __forceinline__ float induced_rec(const float (&rec)[PackLayout<C>::stride], float Z, float fa,
+__device__ __forceinline__ float induced_rec(const float (&rec)[PackLayout<C>::stride], float Z, float Zfa,
                                              const float (&tau)[C]) {
     using PL = PackLayout<C>;
-    int nq = __float_as_int(rec[PL::count]);
-    float mq = rec[PL::minz];
     float dot = 0.f;
 #pragma unroll
     for (int ch = 0; ch < C; ++ch) dot = __fmaf_rn(rec[ch], tau[ch], dot);
     float t = dot - rec[PL::gdot];
-    float factor = __builtin_amdgcn_rcpf((float)(nq + 1));
-    factor = (__fmul_rn(Z, fa) < mq) ? 1.0f : factor;
-    factor = (Z > __fmul_rn(mq, fa)) ? 0.0f : factor;
-    factor = (nq == 0) ? 1.0f : factor;
+    float factor = __builtin_amdgcn_rcpf(rec[PL::count] + 1.0f);
+    factor = (Zfa < rec[PL::minz]) ? 1.0f : factor;        // in front, or q empty
+    factor = (Z > rec[PL::behind]) ? 0.0f : factor;        // hidden behind q
     return factor * t;
 }
 
@@ -598,14 +598,15 @@ __device__ __forceinline__ void layer_work(const float* __restrict__ pack, uint3
     load_rec<C>(pack, hd ? (uint64_t)pix + lw : (uint64_t)pix, rd);
     load_rec<C>(pack, hu ? (uint64_t)pix - lw : (uint64_t)pix, ru);
     if (vis) {
-        float inv = __builtin_amdgcn_rcpf((float)__float_as_int(own[PL::count]));
+        float inv = __builtin_amdgcn_rcpf(own[PL::count]);
 #pragma unroll
         for (int ch = 0; ch < C; ++ch) dt[ch] = __fmaf_rn(own[ch], inv, dt[ch]);
     }
-    float tr = hr ? induced_rec<C>(rr, Z, fa, tau) : 0.f;
-    float tl = hl ? induced_rec<C>(rl, Z, fa, tau) : 0.f;
-    float td = hd ? induced_rec<C>(rd, Z, fa, tau) : 0.f;
-    float tu = hu ? induced_rec<C>(ru, Z, fa, tau) : 0.f;
+    const float Zfa = __fmul_rn(Z, fa);
+    float tr = hr ? induced_rec<C>(rr, Z, Zfa, tau) : 0.f;
+    float tl = hl ? induced_rec<C>(rl, Z, Zfa, tau) : 0.f;
+    float td = hd ? induced_rec<C>(rd, Z, Zfa, tau) : 0.f;
+    float tu = hu ? induced_rec<C>(ru, Z, Zfa, tau) : 0.f;
     du = tr - tl;
     dv = td - tu;
 }
@@ -638,12 +639,12 @@ __device__ __forceinline__ void point_view(const Cam& c, int L, float fa, bool s
                 int qx = 0, qy = 0;
                 uint32_t pix = 0;
                 in[l] = layer_pixel(c, true, l, p.u0, p.v0, qx, qy, pix);
-                mz[l] = pack[(uint64_t)pix * PL::stride + PL::minz];   // pix is valid for every lane
+                mz[l] = pack[(uint64_t)pix * PL::stride + PL::behind];   // pix is valid for every lane
             }
         }
 #pragma unroll
         for (int l = 0; l < kMaxLayers; ++l) {
-            const bool vis = in[l] && p.Z <= __fmul_rn(mz[l], fa);
+            const bool vis = in[l] && p.Z <= mz[l];   // Eq. depthtest against (1+alpha) min_z
             seen |= (uint32_t)vis << l;
             work |= (uint32_t)(vis || (spatial_all && in[l])) << l;
         }
@@ -668,8 +669,8 @@ __device__ __forceinline__ void point_view(const Cam& c, int L, float fa, bool s
         uint32_t pix = 0;
         const bool in = layer_pixel_at(true, l, lw, lh, base, p.u0, p.v0, qx, qy, pix);
         base += (uint32_t)lw * (uint32_t)lh;
-        const float mz = pack[(uint64_t)pix * PL::stride + PL::minz];   // pix is valid for every lane
-        const bool vis = in && p.Z <= __fmul_rn(mz, fa);
+        const float mz = pack[(uint64_t)pix * PL::stride + PL::behind];   // pix is valid for every lane
+        const bool vis = in && p.Z <= mz;
         if (!(vis || (spatial_all && in))) continue;
 #endif
         float du = 0.f, dv = 0.f;
@@ -948,7 +949,7 @@ template <int C, typename S>
 static hipError_t backward_impl(const BwdArgs& a, hipStream_t st) {
     dim3 gn((unsigned)std::min<int64_t>((a.max_layer_pixels + 255) / 256, 1024), (unsigned)(a.V * a.L));
     a.timer.mark(kKPack, 0, st);
-    k_pack<C><<<gn, 256, 0, st>>>(a.views, a.L, a.keys, a.counts, a.images, a.grad, a.pack,
+    k_pack<C><<<gn, 256, 0, st>>>(a.views, a.L, a.keys, a.counts, a.images, a.grad, a.pack, a.fa,
                                  make_bg(a.background, C));
     a.timer.mark(kKPack, 1, st);
     unsigned g = a.V == 1 ? backward_points<C, S, true>(a, st) : backward_points<C, S, false>(a, st);
