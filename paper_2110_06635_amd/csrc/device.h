@@ -177,6 +177,65 @@ __device__ __forceinline__ void wave_sum_n(float (&v)[N]) {
     for (int i = 0; i < N; ++i) v[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[i]), 63));
 }
 
+// Segmented sums over runs of consecutive lanes that hold the same key
+// (every lane must be active).  Lanes whose key is `none` carry zeros.  On
+// return the last lane of each run holds the run's totals in v and the
+// function returns true there (false on every other lane and on runs of
+// `none`).  In-row Hillis-Steele steps (shift 1, 2, 4, 8) followed by the two
+// row broadcasts, each combining (v, f) pairs as (f ? v : v + v_left,
+// f | f_left) with f = "a run starts at or after the source lane".
+template <int N>
+__device__ __forceinline__ bool run_sums(uint32_t key, uint32_t none, float (&v)[N]) {
+    const int lane = __lane_id();
+    const uint32_t prev = (uint32_t)__builtin_amdgcn_ds_bpermute((lane - 1) << 2, (int)key);
+    const uint32_t next = (uint32_t)__builtin_amdgcn_ds_bpermute((lane + 1) << 2, (int)key);
+    uint32_t f = (lane == 0 || prev != key) ? 1u : 0u;
+#define ADOP_RUN_STEP(CTRL, RM, BC)                                                            \
+    {                                                                                        \
+        const uint32_t fl = dpp_u32<CTRL, RM, BC>(0u, f);                                    \
+        _Pragma("unroll") for (int i = 0; i < N; ++i) {                                      \
+            const float vl = __uint_as_float(dpp_u32<CTRL, RM, BC>(0u, __float_as_uint(v[i]))); \
+            v[i] = f ? v[i] : v[i] + vl;                                                     \
+        }                                                                                    \
+        f |= fl;                                                                             \
+    }
+    ADOP_RUN_STEP(0x111, 0xf, true)
+    ADOP_RUN_STEP(0x112, 0xf, true)
+    ADOP_RUN_STEP(0x114, 0xf, true)
+    ADOP_RUN_STEP(0x118, 0xf, true)
+    ADOP_RUN_STEP(0x142, 0xa, false)
+    ADOP_RUN_STEP(0x143, 0xc, false)
+#undef ADOP_RUN_STEP
+    return key != none && (lane == 63 || next != key);
+}
+
+// Segmented minimum of 64-bit values over runs of equal keys, with the
+// same steps as run_sums; lanes whose key is `none` carry ~0.  Returns true
+// on the last lane of each run, which then holds the run's minimum.
+__device__ __forceinline__ bool run_min_u64(uint32_t key, uint32_t none, uint64_t& v) {
+    const int lane = __lane_id();
+    const uint32_t prev = (uint32_t)__builtin_amdgcn_ds_bpermute((lane - 1) << 2, (int)key);
+    const uint32_t next = (uint32_t)__builtin_amdgcn_ds_bpermute((lane + 1) << 2, (int)key);
+    uint32_t f = (lane == 0 || prev != key) ? 1u : 0u;
+#define ADOP_RUN_STEP(CTRL, RM, BC)                                                  \
+    {                                                                              \
+        const uint32_t fl = dpp_u32<CTRL, RM, BC>(0u, f);                          \
+        const uint32_t lo = dpp_u32<CTRL, RM, BC>(0xffffffffu, (uint32_t)v);       \
+        const uint32_t hi = dpp_u32<CTRL, RM, BC>(0xffffffffu, (uint32_t)(v >> 32)); \
+        const uint64_t o = ((uint64_t)hi << 32) | lo;                              \
+        v = (!f && o < v) ? o : v;                                                 \
+        f |= fl;                                                                   \
+    }
+    ADOP_RUN_STEP(0x111, 0xf, false)
+    ADOP_RUN_STEP(0x112, 0xf, false)
+    ADOP_RUN_STEP(0x114, 0xf, false)
+    ADOP_RUN_STEP(0x118, 0xf, false)
+    ADOP_RUN_STEP(0x142, 0xa, false)
+    ADOP_RUN_STEP(0x143, 0xc, false)
+#undef ADOP_RUN_STEP
+    return key != none && (lane == 63 || next != key);
+}
+
 template <int CTRL, int ROWMASK, bool BOUND>
 __device__ __forceinline__ double dpp_f64(double v) {
     uint64_t u = (uint64_t)__double_as_longlong(v);

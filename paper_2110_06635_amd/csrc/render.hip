@@ -76,6 +76,15 @@ namespace adop {
 #ifndef ADOP_ACC_WCACHE
 #define ADOP_ACC_WCACHE 1
 #endif
+// ADOP_DEPTH_RUNS 1: the same for the depth pass (segmented minima)
+#ifndef ADOP_DEPTH_RUNS
+#define ADOP_DEPTH_RUNS 1
+#endif
+// ADOP_ACC_RUNS 1: a wave whose passing points fall into several pixels
+// sums runs of equal pixels with a segmented DPP scan instead of grouping
+#ifndef ADOP_ACC_RUNS
+#define ADOP_ACC_RUNS 1
+#endif
 #ifndef ADOP_PPL4
 #define ADOP_PPL4 4
 #endif
@@ -196,8 +205,14 @@ __device__ __forceinline__ void depth_point(const Cam& c, int L, bool live, floa
         if (ballot(want && pix[l] != p0) == 0) {
             uint64_t k = wave_min_u64(want ? key : ~0ull);
             if (lane_id() == leader) atomic_min_u64(keys + p0, k);
-        } else if (want) {
-            atomic_min_u64(keys + pix[l], key);
+        } else {
+#if ADOP_DEPTH_RUNS
+            // several pixels: segmented minima over runs of equal pixels
+            uint64_t k = want ? key : ~0ull;
+            if (run_min_u64(want ? pix[l] : kEmptySlot, kEmptySlot, k)) atomic_min_u64(keys + pix[l], k);
+#else
+            if (want) atomic_min_u64(keys + pix[l], key);
+#endif
         }
     }
 #endif
@@ -340,6 +355,39 @@ __device__ __forceinline__ void accum_update(bool pass, uint32_t pix, const floa
     uint64_t rem = ballot(pass);
     if (rem == 0) return;
     const int lane = lane_id();
+#if ADOP_ACC_RUNS
+    {
+        // one pixel for every passing lane: one wave sum; otherwise segmented
+        // sums over runs of equal pixels, one update per run
+        const int leader = __builtin_ctzll(rem);
+        const uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pix, leader);
+        const uint64_t mm = ballot(pass && pix == p0);
+        if (mm == rem) {
+            float s[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) s[c] = pass ? f[c] : 0.0f;
+            wave_sum_n<C>(s);
+            const int k = __builtin_popcountll(mm);
+#if ADOP_ACC_WCACHE
+            wcache_add<C>(w, p0, s, k, t, sums, counts);
+#else
+            if (lane == leader) table_add<C>(t, sums, counts, p0, s, k);
+#endif
+            return;
+        }
+        float v[C + 1];
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[c] = pass ? f[c] : 0.0f;
+        v[C] = pass ? 1.0f : 0.0f;
+        if (run_sums<C + 1>(pass ? pix : kEmptySlot, kEmptySlot, v)) {
+            float s[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) s[c] = v[c];
+            table_add<C>(t, sums, counts, pix, s, (int32_t)v[C]);
+        }
+        return;
+    }
+#endif
 #pragma unroll 1
     for (int it = 0; it < kMaxGroups && rem != 0; ++it) {
         int leader = __builtin_ctzll(rem);
