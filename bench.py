@@ -45,11 +45,12 @@ def sources_sha256():
     return h.hexdigest()
 
 
-def recorded_traffic(kernel, workload, storage):
-    """HBM bytes per launch of `kernel` from the FETCH_SIZE / WRITE_SIZE
-    counter runs kept under profiles/ (each scaled by its copy-kernel factor),
-    or None when no record matches this workload or the kernel sources have
-    changed since the counters were taken."""
+def recorded_counters(kernel, workload, storage):
+    """Counter record of `kernel` kept under profiles/: HBM bytes per launch
+    from the FETCH_SIZE / WRITE_SIZE runs (each scaled by its copy-kernel
+    factor) and VALU instructions per launch, or None when no record matches
+    this workload or the kernel sources have changed since the counters were
+    taken."""
     try:
         with open(TRAFFIC_RECORD) as f:
             rec = json.load(f)
@@ -59,8 +60,11 @@ def recorded_traffic(kernel, workload, storage):
         return None
     if rec.get("sources_sha256") != sources_sha256():
         return None
-    k = rec.get("kernels", {}).get(kernel)
-    return int(k["bytes_per_launch"]) if k else None
+    return rec.get("kernels", {}).get(kernel)
+
+
+# one wave64 VALU instruction per CU per cycle: 256 CUs x 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 2.4e9
 
 
 def algorithmic_bytes(n, C, s, phi, P):
@@ -297,10 +301,18 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["avg_ms"])
     achieved = ab[dom] / (kern[dom]["avg_ms"] * 1e-3) / 1e9
     step_bytes = sum(ab.values())
+    rec = recorded_counters(dom, s.name, args.dtype)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": recorded_traffic(dom, s.name, args.dtype), "traffic_unit": "HBM bytes per launch",
+                "traffic": int(rec["bytes_per_launch"]) if rec and "bytes_per_launch" in rec else None,
+                "traffic_unit": "HBM bytes per launch",
                 "algorithmic_bytes": int(ab[dom])}
+    alu_issue = None
+    if rec and "valu_insts" in rec:
+        t = kern[dom]["avg_ms"] * 1e-3
+        alu_issue = {"kernel": dom, "valu_insts_per_launch": rec["valu_insts"],
+                     "achieved": round(rec["valu_insts"] / t / 1e9, 1), "peak": VALU_ISSUE_PEAK / 1e9,
+                     "unit": "G wave-instructions/s", "frac": round(rec["valu_insts"] / t / VALU_ISSUE_PEAK, 4)}
     variants = {}
     for vd in [v for v in args.variants.split(",") if v and v != args.dtype]:
         log(f"timing variant {vd}")
@@ -336,6 +348,7 @@ def main():
         "coverage": round(r["coverage"], 5),
         "kernels_ms": {k: round(v["avg_ms"], 4) for k, v in kern.items()},
         "roofline": roofline,
+        "alu_issue": alu_issue,
         "cpu_baseline": cpu,
         "precision_variants": variants,
     }

@@ -413,6 +413,18 @@ __device__ __forceinline__ RangeMap range_map(int64_t n, int64_t chunk) {
     return m;
 }
 
+// Several views, one per workgroup: workgroup b renders view b % V of point
+// range b / V; the ranges are contiguous and in dispatch order.
+__device__ __forceinline__ RangeMap range_map_views(int64_t n, int64_t chunk, int V) {
+    RangeMap m;
+    const int64_t nc = (n + chunk - 1) / chunk;
+    const int64_t G = (int64_t)(gridDim.x / (unsigned)V);
+    const int64_t g = (int64_t)(blockIdx.x / (unsigned)V);
+    m.c0 = nc * g / G;
+    m.c1 = nc * (g + 1) / G;
+    return m;
+}
+
 // ----------------------------------------------------------------------------
 // workgroup-private open-addressing tables in LDS (pixel -> partial result)
 // ----------------------------------------------------------------------------

@@ -80,6 +80,11 @@ namespace adop {
 #ifndef ADOP_DEPTH_RUNS
 #define ADOP_DEPTH_RUNS 1
 #endif
+// chunks between write-outs of the accumulation's workgroup table (0: only
+// at the end of the workgroup's range)
+#ifndef ADOP_ACC_WINDOW
+#define ADOP_ACC_WINDOW 0
+#endif
 // ADOP_ACC_RUNS 1: a wave whose passing points fall into several pixels
 // sums runs of equal pixels with a segmented DPP scan instead of grouping
 #ifndef ADOP_ACC_RUNS
@@ -266,6 +271,7 @@ __global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_DEPTH_WPE) k_depth(con
 }
 
 // ---- accumulation pass ----------------------------------------------------
+constexpr int kAccWindow = ADOP_ACC_WINDOW;
 constexpr int kMaxGroups = ADOP_MAX_GROUPS;
 constexpr int kMinGroup = ADOP_MIN_GROUP;
 
@@ -420,6 +426,7 @@ __device__ __forceinline__ void acc_table_clear(AccTable<C>& t) {
     }
 }
 
+// Adds every occupied slot to the global sums and counts and empties it.
 template <int C>
 __device__ __forceinline__ void acc_table_flush(AccTable<C>& t, float* __restrict__ sums, int32_t* __restrict__ counts) {
     for (int j = threadIdx.x; j < AccTable<C>::H; j += blockDim.x) {
@@ -427,8 +434,13 @@ __device__ __forceinline__ void acc_table_flush(AccTable<C>& t, float* __restric
         if (k != kEmptySlot) {
             float* dst = sums + (uint64_t)k * C;
 #pragma unroll
-            for (int c = 0; c < C; ++c) atomic_add_f32(dst + c, t.sum[c][j]);
+            for (int c = 0; c < C; ++c) {
+                atomic_add_f32(dst + c, t.sum[c][j]);
+                t.sum[c][j] = 0.f;
+            }
             atomic_add_i32(counts + k, t.cnt[j]);
+            t.cnt[j] = 0;
+            t.key[j] = kEmptySlot;
         }
     }
 }
@@ -470,7 +482,12 @@ __device__ __forceinline__ void accum_point(const Cam& c, int L, float fa, bool 
     }
 }
 
-template <int C, typename S, bool SINGLE>
+// One view per workgroup: with V views the grid holds V workgroups per
+// point range (view = block % V), so every workgroup's table and wave cache
+// see one view's pixels; the V workgroups of a range are dispatched together
+// and read its points while they are in the caches.  The workgroup table is
+// written out every kAccWindow chunks, before it fills.
+template <int C, typename S>
 __global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_ACCUM_WPE) k_accum(const float* __restrict__ xs, const float* __restrict__ ys,
                                                const float* __restrict__ zs, const void* __restrict__ feat,
                                                int64_t n, const ViewRec* __restrict__ views, int V, int L,
@@ -483,8 +500,10 @@ __global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_ACCUM_WPE) k_accum(con
     WaveCache<C> w;
     wcache_init<C>(w);
 #endif
-    const Cam c0 = load_cam(views);
-    RangeMap m = range_map(n, kBlock);
+    const int view = V > 1 ? (int)(blockIdx.x % (unsigned)V) : 0;
+    const Cam c0 = load_cam(views + view);
+    RangeMap m = V > 1 ? range_map_views(n, kBlock, V) : range_map(n, kBlock);
+    int since = 0;
     // the next chunk's points are loaded while the current one is processed
     float nx = 0.f, ny = 0.f, nz = 0.f, nf[C];
 #pragma unroll
@@ -508,11 +527,12 @@ __global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_ACCUM_WPE) k_accum(con
 #pragma unroll
         for (int ch = 0; ch < C; ++ch) f[ch] = nf[ch];
         if (c + 1 < m.c1) fetch(c + 1);
-        if (SINGLE) {
-            accum_point<C>(c0, L, fa, live, x, y, z, f, keys32, t, sums, counts ADOP_WC_ARG);
-        } else {
-            for (int v = 0; v < V; ++v)
-                accum_point<C>(load_cam(views + v), L, fa, live, x, y, z, f, keys32, t, sums, counts ADOP_WC_ARG);
+        accum_point<C>(c0, L, fa, live, x, y, z, f, keys32, t, sums, counts ADOP_WC_ARG);
+        if (kAccWindow > 0 && ++since == kAccWindow) {   // uniform in the workgroup
+            since = 0;
+            __syncthreads();
+            acc_table_flush<C>(t, sums, counts);
+            __syncthreads();
         }
     }
 #if ADOP_ACC_WCACHE
@@ -950,14 +970,20 @@ static inline unsigned persistent_grid(int64_t n, int64_t chunk, int cus, int pe
 template <int C, typename S, bool SINGLE>
 static void forward_points(const FwdArgs& a, hipStream_t st) {
     static const int occ_depth = resident(k_depth<SINGLE>, 0);
-    static const int occ_accum = resident(k_accum<C, S, SINGLE>, 0);
+    static const int occ_accum = resident(k_accum<C, S>, 0);
     unsigned gd = persistent_grid(a.n, kBlock, a.cus, occ_depth, 1 << 20);
     a.timer.mark(kKDepth, 0, st);
     k_depth<SINGLE><<<gd, kBlock, 0, st>>>(a.x, a.y, a.z, a.orig, a.n, a.views, a.V, a.L, a.keys);
     a.timer.mark(kKDepth, 1, st);
     unsigned ga = persistent_grid(a.n, kBlock, a.cus, occ_accum, 1 << 20);
+    if (!SINGLE) {
+        // V workgroups (one per view) per point range
+        int64_t ranges = std::max<int64_t>(kXcds, (int64_t)ga / a.V / kXcds * kXcds);
+        ranges = std::min<int64_t>(ranges, (a.n + kBlock - 1) / kBlock);
+        ga = (unsigned)(std::max<int64_t>(ranges, 1) * a.V);
+    }
     a.timer.mark(kKAccum, 0, st);
-    k_accum<C, S, SINGLE><<<ga, kBlock, 0, st>>>(a.x, a.y, a.z, a.feat, a.n, a.views, a.V, a.L, a.fa,
+    k_accum<C, S><<<ga, kBlock, 0, st>>>(a.x, a.y, a.z, a.feat, a.n, a.views, a.V, a.L, a.fa,
                                                   reinterpret_cast<const uint32_t*>(a.keys), a.sums, a.counts);
     a.timer.mark(kKAccum, 1, st);
 }
@@ -1031,12 +1057,16 @@ int backward_points_per_group(int C) { return kBlock * (C <= 4 ? ADOP_PPL4 : 2);
     }
 
 #ifdef ADOP_TUNE_C4_F32_ONLY
-// tuning builds: only 4 channels, FP32 storage
+// tuning builds: only 4 channels FP32 and 8 channels BF16
 hipError_t launch_forward(const FwdArgs& a, hipStream_t st) {
-    return (a.C == 4 && a.dtype == 0) ? forward_impl<4, F32>(a, st) : hipErrorInvalidValue;
+    if (a.C == 4 && a.dtype == 0) return forward_impl<4, F32>(a, st);
+    if (a.C == 8 && a.dtype == 1) return forward_impl<8, BF16>(a, st);
+    return hipErrorInvalidValue;
 }
 hipError_t launch_backward(const BwdArgs& a, hipStream_t st) {
-    return (a.C == 4 && a.dtype == 0) ? backward_impl<4, F32>(a, st) : hipErrorInvalidValue;
+    if (a.C == 4 && a.dtype == 0) return backward_impl<4, F32>(a, st);
+    if (a.C == 8 && a.dtype == 1) return backward_impl<8, BF16>(a, st);
+    return hipErrorInvalidValue;
 }
 #else
 hipError_t launch_forward(const FwdArgs& a, hipStream_t st) {
