@@ -32,8 +32,8 @@ static float u2f(uint32_t u) { float f; memcpy(&f, &u, 4); return f; }
 /*   x_d = a D + 2 p1 a b + p2 (r2 + 2 a^2),  y_d = b D + 2 p2 a b + p1 (r2 + 2 b^2),
  *   u0 = fx x_d + cx,  v0 = fy y_d + cy.                                     */
 /* ------------------------------------------------------------------------ */
-int oracle_project(const oracle_camera* cam, float x, float y, float z,
-                   float* Zo, float* u0o, float* v0o)
+static int project_full(const oracle_camera* cam, float x, float y, float z,
+                        float* Xo, float* Yo, float* Zo, float* u0o, float* v0o)
 {
     const float* R = cam->R;
     float X = fmaf(R[0], x, fmaf(R[1], y, fmaf(R[2], z, cam->t[0])));
@@ -54,8 +54,49 @@ int oracle_project(const oracle_camera* cam, float x, float y, float z,
     float u0 = fmaf(cam->fx, xd, cam->cx);
     float v0 = fmaf(cam->fy, yd, cam->cy);
     if (!isfinite(u0) || !isfinite(v0)) return 0;
-    *Zo = Z; *u0o = u0; *v0o = v0;
+    *Xo = X; *Yo = Y; *Zo = Z; *u0o = u0; *v0o = v0;
     return 1;
+}
+
+int oracle_project(const oracle_camera* cam, float x, float y, float z,
+                   float* Zo, float* u0o, float* v0o)
+{
+    float X, Y;
+    return project_full(cam, x, y, z, &X, &Y, Zo, u0o, v0o);
+}
+
+static const oracle_options no_options = { 0u, NULL, NULL, NULL, 0.0f };
+
+/* Eq. normalculling for point i in a view (see ORACLE_CULL_*). */
+static int kept_by_normal(const oracle_camera* cam, const oracle_options* opt, int64_t i,
+                          float X, float Y, float Z)
+{
+    if (!(opt->flags & (ORACLE_CULL_BACKFACE | ORACLE_CULL_PRINTED))) return 1;
+    const float* R = cam->R;
+    const float* nv = &opt->normals[3 * i];
+    float m0 = fmaf(R[0], nv[0], fmaf(R[1], nv[1], R[2] * nv[2]));
+    float m1 = fmaf(R[3], nv[0], fmaf(R[4], nv[1], R[5] * nv[2]));
+    float m2 = fmaf(R[6], nv[0], fmaf(R[7], nv[1], R[8] * nv[2]));
+    float d = fmaf(m0, X, fmaf(m1, Y, m2 * Z));
+    if (opt->flags & ORACLE_CULL_BACKFACE) return d < 0.0f;
+    return d > 0.0f;
+}
+
+/* Eq. discard for point i at layer l. */
+static int kept_at_layer(const oracle_camera* cam, const oracle_options* opt, int64_t i, float Z, int l)
+{
+    if (!(opt->flags & ORACLE_DISCARD)) return 1;
+    float s0 = (cam->fx * opt->radius[i]) / Z;
+    float lhs = ldexpf(s0, -l) * opt->gamma;
+    float rhs = sqrtf(1.0f - opt->beta[i]);
+    return lhs > rhs;
+}
+
+/* Feature channel ch of point i as rendered (exp of a logarithmic one). */
+static double feat_val(const oracle_options* opt, const float* feat, int64_t i, int c, int ch)
+{
+    double f = (double)feat[i * c + ch];
+    return (opt->flags & ORACLE_LOG_FEATURES) ? exp(f) : f;
 }
 
 void oracle_project_points(const oracle_camera* cam, int64_t n, const float* pos,
@@ -132,7 +173,7 @@ typedef struct {
  *   (Eq. depthtest, evaluated in binary32 with fa = 1 + alpha). */
 static int rasterize(int64_t n, int32_t c, const float* pos, const float* feat,
                      int32_t V, const oracle_camera* cams, int32_t L, float alpha,
-                     uint64_t* keys_out, int32_t* counts_out, raster_state* st)
+                     const oracle_options* opt, uint64_t* keys_out, int32_t* counts_out, raster_state* st)
 {
     const float fa = 1.0f + alpha;
     st->total = oracle_total_pixels(cams, V, L);
@@ -149,12 +190,14 @@ static int rasterize(int64_t n, int32_t c, const float* pos, const float* feat,
     for (int v = 0; v < V; ++v) {
         const oracle_camera* cam = &cams[v];
         for (int64_t i = 0; i < n; ++i) {
-            float Z, u0, v0;
-            if (!oracle_project(cam, pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], &Z, &u0, &v0)) continue;
+            float X, Y, Z, u0, v0;
+            if (!project_full(cam, pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], &X, &Y, &Z, &u0, &v0)) continue;
+            if (!kept_by_normal(cam, opt, i, X, Y, Z)) continue;
             uint64_t key = ((uint64_t)f2u(Z) << 32) | (uint64_t)(uint32_t)i;
             for (int l = 0; l < L; ++l) {
                 int32_t px, py;
                 if (!oracle_layer_pixel(cam, u0, v0, l, &px, &py)) continue;
+                if (!kept_at_layer(cam, opt, i, Z, l)) continue;
                 int64_t idx = st->vbase[v] + layer_offset(cam, l) + (int64_t)py * (cam->width >> l) + px;
                 if (key < st->keys[idx]) st->keys[idx] = key;
             }
@@ -164,17 +207,19 @@ static int rasterize(int64_t n, int32_t c, const float* pos, const float* feat,
     for (int v = 0; v < V; ++v) {
         const oracle_camera* cam = &cams[v];
         for (int64_t i = 0; i < n; ++i) {
-            float Z, u0, v0;
-            if (!oracle_project(cam, pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], &Z, &u0, &v0)) continue;
+            float X, Y, Z, u0, v0;
+            if (!project_full(cam, pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], &X, &Y, &Z, &u0, &v0)) continue;
+            if (!kept_by_normal(cam, opt, i, X, Y, Z)) continue;
             for (int l = 0; l < L; ++l) {
                 int32_t px, py;
                 if (!oracle_layer_pixel(cam, u0, v0, l, &px, &py)) continue;
+                if (!kept_at_layer(cam, opt, i, Z, l)) continue;
                 int64_t idx = st->vbase[v] + layer_offset(cam, l) + (int64_t)py * (cam->width >> l) + px;
                 float minz = u2f((uint32_t)(st->keys[idx] >> 32));
                 float thr = minz * fa;
                 if (Z <= thr) {
                     st->counts[idx] += 1;
-                    for (int ch = 0; ch < c; ++ch) st->sums[idx * c + ch] += (double)feat[i * c + ch];
+                    for (int ch = 0; ch < c; ++ch) st->sums[idx * c + ch] += feat_val(opt, feat, i, c, ch);
                 }
             }
         }
@@ -199,14 +244,32 @@ static double blended(const raster_state* st, int64_t idx, int c, int ch, const 
     return st->sums[idx * c + ch] / (double)k;
 }
 
+static int check_options(int64_t n, const oracle_options* opt)
+{
+    uint32_t f = opt->flags;
+    if ((f & ORACLE_CULL_BACKFACE) && (f & ORACLE_CULL_PRINTED)) return 1;
+    if ((f & (ORACLE_CULL_BACKFACE | ORACLE_CULL_PRINTED)) && n > 0 && !opt->normals) return 1;
+    if ((f & ORACLE_DISCARD) && n > 0 && (!opt->radius || !opt->beta || !(opt->gamma > 0.0f))) return 1;
+    return 0;
+}
+
 int oracle_forward(int64_t n, int32_t c, const float* pos, const float* feat,
                    int32_t V, const oracle_camera* cams, int32_t L, float alpha,
                    const float* background, uint64_t* keys, int32_t* counts,
                    float* images, double* images64)
 {
-    if (check_args(n, c, V, cams, L)) return 1;
+    return oracle_forward_ex(n, c, pos, feat, V, cams, L, alpha, &no_options, background, keys, counts,
+                             images, images64);
+}
+
+int oracle_forward_ex(int64_t n, int32_t c, const float* pos, const float* feat,
+                      int32_t V, const oracle_camera* cams, int32_t L, float alpha,
+                      const oracle_options* opt, const float* background, uint64_t* keys,
+                      int32_t* counts, float* images, double* images64)
+{
+    if (check_args(n, c, V, cams, L) || check_options(n, opt)) return 1;
     raster_state st;
-    if (rasterize(n, c, pos, feat, V, cams, L, alpha, keys, counts, &st)) return 2;
+    if (rasterize(n, c, pos, feat, V, cams, L, alpha, opt, keys, counts, &st)) return 2;
     for (int v = 0; v < V; ++v) {
         const oracle_camera* cam = &cams[v];
         for (int l = 0; l < L; ++l) {
@@ -238,7 +301,7 @@ int oracle_forward(int64_t n, int32_t c, const float* pos, const float* feat,
  * the neighbour's min_z, comparisons in binary32.  Returns <G(q), dI> and
  * writes a magnitude bound of that dot product into *mag. */
 static double induced(const raster_state* st, const oracle_camera* cam, int v, int l, int c,
-                      int32_t qx, int32_t qy, float Z, float fa, const float* tau,
+                      int32_t qx, int32_t qy, float Z, float fa, const double* tau,
                       const float* background, const float* grad, double* mag)
 {
     int32_t wl = cam->width >> l, hl = cam->height >> l;
@@ -251,9 +314,9 @@ static double induced(const raster_state* st, const oracle_camera* cam, int v, i
         /* case 1: background is replaced by the point's texture */
         for (int ch = 0; ch < c; ++ch) {
             double g = (double)grad[img_index(st, cam, v, l, c, ch, qx, qy)];
-            double dI = (double)tau[ch] - (double)background[ch];
+            double dI = tau[ch] - (double)background[ch];
             dot += g * dI;
-            m += fabs(g) * (fabs((double)tau[ch]) + fabs((double)background[ch]));
+            m += fabs(g) * (fabs(tau[ch]) + fabs((double)background[ch]));
         }
         *mag = m;
         return dot;
@@ -266,8 +329,8 @@ static double induced(const raster_state* st, const oracle_camera* cam, int v, i
         for (int ch = 0; ch < c; ++ch) {
             double g = (double)grad[img_index(st, cam, v, l, c, ch, qx, qy)];
             double I = blended(st, q, c, ch, background);
-            dot += g * ((double)tau[ch] - I);
-            m += fabs(g) * (fabs((double)tau[ch]) + fabs(I));
+            dot += g * (tau[ch] - I);
+            m += fabs(g) * (fabs(tau[ch]) + fabs(I));
         }
         *mag = m;
         return dot;
@@ -276,9 +339,9 @@ static double induced(const raster_state* st, const oracle_camera* cam, int v, i
     for (int ch = 0; ch < c; ++ch) {
         double g = (double)grad[img_index(st, cam, v, l, c, ch, qx, qy)];
         double I = blended(st, q, c, ch, background);
-        double Inew = ((double)nq * I + (double)tau[ch]) / (double)(nq + 1);
+        double Inew = ((double)nq * I + tau[ch]) / (double)(nq + 1);
         dot += g * (Inew - I);
-        m += fabs(g) * (fabs((double)tau[ch]) + fabs(I)) / (double)(nq + 1);
+        m += fabs(g) * (fabs(tau[ch]) + fabs(I)) / (double)(nq + 1);
     }
     *mag = m;
     return dot;
@@ -291,14 +354,28 @@ int oracle_backward(int64_t n, int32_t c, const float* pos, const float* feat,
                     double* dfeat_abs, double* dpos_abs, double* dpose_abs,
                     double* dintr_abs, double* gu_out, double* gv_out)
 {
-    if (check_args(n, c, V, cams, L)) return 1;
+    oracle_options opt = no_options;
+    opt.flags = flags & ORACLE_SPATIAL_ALL;
+    return oracle_backward_ex(n, c, pos, feat, V, cams, L, alpha, &opt, background, grad, dfeat, dpos,
+                              dpose, dintr, dfeat_abs, dpos_abs, dpose_abs, dintr_abs, gu_out, gv_out);
+}
+
+int oracle_backward_ex(int64_t n, int32_t c, const float* pos, const float* feat,
+                       int32_t V, const oracle_camera* cams, int32_t L, float alpha,
+                       const oracle_options* opt, const float* background, const float* grad,
+                       double* dfeat, double* dpos, double* dpose, double* dintr,
+                       double* dfeat_abs, double* dpos_abs, double* dpose_abs,
+                       double* dintr_abs, double* gu_out, double* gv_out)
+{
+    if (check_args(n, c, V, cams, L) || check_options(n, opt)) return 1;
+    const uint32_t flags = opt->flags;
     const float fa = 1.0f + alpha;
     int64_t total = oracle_total_pixels(cams, V, L);
     uint64_t* keys = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(total + 1));
     int32_t* counts = (int32_t*)malloc(sizeof(int32_t) * (size_t)(total + 1));
     if (!keys || !counts) { free(keys); free(counts); return 2; }
     raster_state st;
-    if (rasterize(n, c, pos, feat, V, cams, L, alpha, keys, counts, &st)) { free(keys); free(counts); return 2; }
+    if (rasterize(n, c, pos, feat, V, cams, L, alpha, opt, keys, counts, &st)) { free(keys); free(counts); return 2; }
 
     memset(dfeat, 0, sizeof(double) * (size_t)(n * c));
     memset(dpos, 0, sizeof(double) * (size_t)(3 * n));
@@ -314,14 +391,17 @@ int oracle_backward(int64_t n, int32_t c, const float* pos, const float* feat,
         const double fx = cam->fx, fy = cam->fy;
         const double k1 = cam->k1, k2 = cam->k2, k3 = cam->k3, p1 = cam->p1, p2 = cam->p2;
         for (int64_t i = 0; i < n; ++i) {
-            float Z, u0, v0;
+            float X, Y, Z, u0, v0;
             if (gu_out) { gu_out[(int64_t)v * n + i] = 0.0; gv_out[(int64_t)v * n + i] = 0.0; }
-            if (!oracle_project(cam, pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], &Z, &u0, &v0)) continue;
-            const float* tau = &feat[i * c];
+            if (!project_full(cam, pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], &X, &Y, &Z, &u0, &v0)) continue;
+            if (!kept_by_normal(cam, opt, i, X, Y, Z)) continue;
+            double tau[16];
+            for (int ch = 0; ch < c; ++ch) tau[ch] = feat_val(opt, feat, i, c, ch);
             double gu = 0.0, gv = 0.0, gu_m = 0.0, gv_m = 0.0;
             for (int l = 0; l < L; ++l) {
                 int32_t px, py;
                 if (!oracle_layer_pixel(cam, u0, v0, l, &px, &py)) continue;
+                if (!kept_at_layer(cam, opt, i, Z, l)) continue;
                 int32_t wl = cam->width >> l;
                 int64_t idx = st.vbase[v] + layer_offset(cam, l) + (int64_t)py * wl + px;
                 float minz = u2f((uint32_t)(st.keys[idx] >> 32));
@@ -332,8 +412,10 @@ int oracle_backward(int64_t n, int32_t c, const float* pos, const float* feat,
                     double k = (double)st.counts[idx];
                     for (int ch = 0; ch < c; ++ch) {
                         double g = (double)grad[img_index(&st, cam, v, l, c, ch, px, py)];
-                        dfeat[i * c + ch] += g / k;
-                        if (dfeat_abs) dfeat_abs[i * c + ch] += fabs(g) / k;
+                        /* logarithmic descriptors: d exp(f) / df = exp(f) */
+                        double chain = (flags & ORACLE_LOG_FEATURES) ? tau[ch] : 1.0;
+                        dfeat[i * c + ch] += g / k * chain;
+                        if (dfeat_abs) dfeat_abs[i * c + ch] += fabs(g) / k * chain;
                     }
                 }
                 if (!visible && !(flags & ORACLE_SPATIAL_ALL)) continue;
@@ -358,10 +440,10 @@ int oracle_backward(int64_t n, int32_t c, const float* pos, const float* feat,
             /* smooth part of the projection in binary64 */
             const float* Rf = cam->R;
             double xw = pos[3 * i], yw = pos[3 * i + 1], zw = pos[3 * i + 2];
-            double X = (double)Rf[0] * xw + (double)Rf[1] * yw + (double)Rf[2] * zw + (double)cam->t[0];
-            double Y = (double)Rf[3] * xw + (double)Rf[4] * yw + (double)Rf[5] * zw + (double)cam->t[1];
+            double Xd = (double)Rf[0] * xw + (double)Rf[1] * yw + (double)Rf[2] * zw + (double)cam->t[0];
+            double Yd = (double)Rf[3] * xw + (double)Rf[4] * yw + (double)Rf[5] * zw + (double)cam->t[1];
             double Zd = (double)Rf[6] * xw + (double)Rf[7] * yw + (double)Rf[8] * zw + (double)cam->t[2];
-            double a = X / Zd, b = Y / Zd;
+            double a = Xd / Zd, b = Yd / Zd;
             double r2 = a * a + b * b, r4 = r2 * r2, r6 = r4 * r2;
             double D = 1.0 + k1 * r2 + k2 * r4 + k3 * r6;
             double Dp = k1 + 2.0 * k2 * r2 + 3.0 * k3 * r4;
@@ -388,7 +470,7 @@ int oracle_backward(int64_t n, int32_t c, const float* pos, const float* feat,
             }
             /* pose tangent xi = (rho, omega), left-multiplied exp(xi) at xi = 0:
              * d x_c / d rho = I,  d x_c / d omega = -[x_c]_x */
-            double xc[3] = { X, Y, Zd };
+            double xc[3] = { Xd, Yd, Zd };
             double cr[3] = { xc[1] * gc[2] - xc[2] * gc[1], xc[2] * gc[0] - xc[0] * gc[2], xc[0] * gc[1] - xc[1] * gc[0] };
             double cr_m[3] = { fabs(xc[1]) * gc_m[2] + fabs(xc[2]) * gc_m[1], fabs(xc[2]) * gc_m[0] + fabs(xc[0]) * gc_m[2],
                                fabs(xc[0]) * gc_m[1] + fabs(xc[1]) * gc_m[0] };
@@ -416,5 +498,30 @@ int oracle_backward(int64_t n, int32_t c, const float* pos, const float* feat,
     free(st.sums);
     free(keys);
     free(counts);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Stochastic discarding preprocess: distance to the 4th-nearest other point */
+/* (Sec. 3.1, "Stochastic Point Discarding"), by brute force.                */
+/* ------------------------------------------------------------------------ */
+int oracle_knn_radius(int64_t n, const float* pos, float* radius)
+{
+    if (n < 5 || !pos || !radius) return 1;
+    for (int64_t i = 0; i < n; ++i) {
+        float best[4] = { INFINITY, INFINITY, INFINITY, INFINITY };   /* ascending */
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            float dx = pos[3 * j] - pos[3 * i];
+            float dy = pos[3 * j + 1] - pos[3 * i + 1];
+            float dz = pos[3 * j + 2] - pos[3 * i + 2];
+            float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            if (!(d2 < best[3])) continue;
+            int k = 3;
+            while (k > 0 && d2 < best[k - 1]) { best[k] = best[k - 1]; --k; }
+            best[k] = d2;
+        }
+        radius[i] = sqrtf(best[3]);
+    }
     return 0;
 }

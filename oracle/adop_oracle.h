@@ -41,6 +41,34 @@ typedef struct oracle_camera {
 } oracle_camera;
 
 #define ORACLE_SPATIAL_ALL 1u   /* spatial gradient for every in-bounds point */
+/* Eq. normalculling: with n the point's normal and x_c = R x + t, the sign
+ * of d = (R n) . x_c decides (dividing by |x_c| > 0 does not change it).
+ * CULL_BACKFACE keeps points whose normal faces the camera (d < 0);
+ * CULL_PRINTED keeps d > 0, the inequality as printed.  R n and d are
+ * evaluated in binary32 with the nesting of the projection:
+ *   m_k = fmaf(R[3k], nx, fmaf(R[3k+1], ny, R[3k+2] * nz)),
+ *   d = fmaf(m_0, X, fmaf(m_1, Y, m_2 * Z)). */
+#define ORACLE_CULL_BACKFACE 2u
+#define ORACLE_CULL_PRINTED 4u
+/* Logarithmic descriptors (Sec. 4, network architecture): features are
+ * stored as log values and rendered as exp(feat); dL/dfeat is the gradient
+ * with respect to the linear value times exp(feat). */
+#define ORACLE_LOG_FEATURES 8u
+/* Stochastic point discarding (Eq. discard): a point is rendered at layer l
+ * only if r_screen / sqrt(1 - beta) > 1 / gamma, with the world radius
+ * projected as r_screen = (fx r_world / Z) 2^-l; evaluated in binary32 as
+ *   (((fx * r) / Z) * 2^-l) * gamma > sqrtf(1 - beta). */
+#define ORACLE_DISCARD 16u
+
+/* Options of the extended passes.  normals [n][3] (culling), radius [n] and
+ * beta [n] (discarding) may be NULL when the matching flag is off. */
+typedef struct oracle_options {
+    uint32_t flags;
+    const float* normals;
+    const float* radius;
+    const float* beta;
+    float gamma;
+} oracle_options;
 
 /* Projection of one point (FP32 arithmetic, stated formula).  Returns 1 and
  * writes depth Z and layer-0 pixel coordinates (u0, v0) if the point is not
@@ -81,6 +109,25 @@ int oracle_backward(int64_t n, int32_t c, const float* pos, const float* feat,
                     double* dfeat, double* dpos, double* dpose, double* dintr,
                     double* dfeat_abs, double* dpos_abs, double* dpose_abs,
                     double* dintr_abs, double* gu, double* gv);
+
+/* The forward and backward passes with options (flags of the backward's
+ * SPATIAL_ALL included in opt->flags). */
+int oracle_forward_ex(int64_t n, int32_t c, const float* pos, const float* feat,
+                      int32_t V, const oracle_camera* cams, int32_t L, float alpha,
+                      const oracle_options* opt, const float* background, uint64_t* keys,
+                      int32_t* counts, float* images, double* images64);
+int oracle_backward_ex(int64_t n, int32_t c, const float* pos, const float* feat,
+                       int32_t V, const oracle_camera* cams, int32_t L, float alpha,
+                       const oracle_options* opt, const float* background, const float* grad,
+                       double* dfeat, double* dpos, double* dpose, double* dintr,
+                       double* dfeat_abs, double* dpos_abs, double* dpose_abs,
+                       double* dintr_abs, double* gu, double* gv);
+
+/* Stochastic discarding preprocess: r_world[i] = distance from point i to its
+ * 4th-nearest other point (brute force), with squared distances in binary32
+ * as fmaf(dx, dx, fmaf(dy, dy, dz * dz)), d = x_j - x_i, and r the correctly
+ * rounded square root of the 4th smallest.  n >= 5. */
+int oracle_knn_radius(int64_t n, const float* pos, float* radius);
 
 #ifdef __cplusplus
 }

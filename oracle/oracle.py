@@ -17,6 +17,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
 SPATIAL_ALL = 1
+CULL_BACKFACE = 2
+CULL_PRINTED = 4
+LOG_FEATURES = 8
+DISCARD = 16
+
+
+class OracleOptions(ct.Structure):
+    _fields_ = [("flags", ct.c_uint32), ("normals", ct.c_void_p), ("radius", ct.c_void_p),
+                ("beta", ct.c_void_p), ("gamma", ct.c_float)]
 
 
 class OracleCamera(ct.Structure):
@@ -46,6 +55,14 @@ def load(path: str):
     L.oracle_backward.restype = ct.c_int
     L.oracle_backward.argtypes = [ct.c_int64, ct.c_int32, P, P, ct.c_int32, P, ct.c_int32,
                                   ct.c_float, ct.c_uint32, P, P, P, P, P, P, P, P, P, P, P, P]
+    L.oracle_forward_ex.restype = ct.c_int
+    L.oracle_forward_ex.argtypes = [ct.c_int64, ct.c_int32, P, P, ct.c_int32, P, ct.c_int32,
+                                    ct.c_float, P, P, P, P, P, P]
+    L.oracle_backward_ex.restype = ct.c_int
+    L.oracle_backward_ex.argtypes = [ct.c_int64, ct.c_int32, P, P, ct.c_int32, P, ct.c_int32,
+                                     ct.c_float, P, P, P, P, P, P, P, P, P, P, P, P, P]
+    L.oracle_knn_radius.restype = ct.c_int
+    L.oracle_knn_radius.argtypes = [ct.c_int64, P, P]
     return L
 
 
@@ -108,9 +125,35 @@ def total_pixels(cams, layers: int) -> int:
     return int(lib().oracle_total_pixels(cc, len(cams), layers))
 
 
+def _options(flags, normals, radius, beta, gamma):
+    """Options record plus the arrays it points to (kept alive by the caller)."""
+    keep = []
+    o = OracleOptions()
+    o.flags = int(flags)
+    for name, arr, shape in (("normals", normals, 3), ("radius", radius, 1), ("beta", beta, 1)):
+        if arr is not None:
+            a = np.ascontiguousarray(arr, dtype=np.float32)
+            keep.append(a)
+            setattr(o, name, a.ctypes.data)
+    o.gamma = float(gamma)
+    return o, keep
+
+
+def knn_radius(pos):
+    """Distance of each point to its 4th-nearest other point (brute force)."""
+    pos = np.ascontiguousarray(pos, dtype=np.float32)
+    out = np.empty(pos.shape[0], np.float32)
+    if lib().oracle_knn_radius(pos.shape[0], _p(pos), _p(out)) != 0:
+        raise ValueError("oracle_knn_radius needs at least 5 points")
+    return out
+
+
 def forward(pos, feat, cams, layers: int, alpha: float = 0.01, background=None,
-            want64: bool = False):
-    """Returns dict(keys uint64, counts int32, images float32[, images64])."""
+            want64: bool = False, flags: int = 0, normals=None, radius=None, beta=None,
+            gamma: float = 0.0):
+    """Returns dict(keys uint64, counts int32, images float32[, images64]).
+    flags: CULL_BACKFACE / CULL_PRINTED (normals [n,3]), LOG_FEATURES,
+    DISCARD (radius [n], beta [n], gamma)."""
     pos = np.ascontiguousarray(pos, dtype=np.float32)
     feat = np.ascontiguousarray(feat, dtype=np.float32)
     n, c = feat.shape
@@ -122,9 +165,10 @@ def forward(pos, feat, cams, layers: int, alpha: float = 0.01, background=None,
     counts = np.empty(total, np.int32)
     images = np.empty(total * c, np.float32)
     images64 = np.empty(total * c, np.float64) if want64 else None
-    rc = lib().oracle_forward(n, c, _p(pos), _p(feat), len(cams), cc, layers,
-                              ct.c_float(alpha), _p(bg), _p(keys), _p(counts), _p(images),
-                              _p(images64))
+    opt, keep = _options(flags, normals, radius, beta, gamma)
+    rc = lib().oracle_forward_ex(n, c, _p(pos), _p(feat), len(cams), cc, layers,
+                                 ct.c_float(alpha), ct.byref(opt), _p(bg), _p(keys), _p(counts),
+                                 _p(images), _p(images64))
     if rc != 0:
         raise ValueError(f"oracle_forward failed ({rc})")
     out = dict(keys=keys, counts=counts, images=images)
@@ -134,7 +178,8 @@ def forward(pos, feat, cams, layers: int, alpha: float = 0.01, background=None,
 
 
 def backward(pos, feat, cams, layers: int, grad, alpha: float = 0.01, background=None,
-             flags: int = 0, want_abs: bool = True, want_g: bool = False):
+             flags: int = 0, want_abs: bool = True, want_g: bool = False, normals=None,
+             radius=None, beta=None, gamma: float = 0.0):
     """Returns dict(dfeat [n,c], dpos [3,n], dpose [V,6], dintr [V,9]) in float64,
     plus *_abs magnitude bounds and per-point gu/gv [V,n] on request."""
     pos = np.ascontiguousarray(pos, dtype=np.float32)
@@ -154,8 +199,9 @@ def backward(pos, feat, cams, layers: int, grad, alpha: float = 0.01, background
     if want_g:
         out.update(gu=np.empty((V, n)), gv=np.empty((V, n)))
     g = out.get
-    rc = lib().oracle_backward(n, c, _p(pos), _p(feat), V, cc, layers, ct.c_float(alpha),
-                               flags, _p(bg), _p(grad), _p(out["dfeat"]), _p(out["dpos"]),
+    opt, keep = _options(flags, normals, radius, beta, gamma)
+    rc = lib().oracle_backward_ex(n, c, _p(pos), _p(feat), V, cc, layers, ct.c_float(alpha),
+                               ct.byref(opt), _p(bg), _p(grad), _p(out["dfeat"]), _p(out["dpos"]),
                                _p(out["dpose"]), _p(out["dintr"]), _p(g("dfeat_abs")),
                                _p(g("dpos_abs")), _p(g("dpose_abs")), _p(g("dintr_abs")),
                                _p(g("gu")), _p(g("gv")))

@@ -1,5 +1,5 @@
 """Planted mistakes: each mutation of the oracle's C source must be caught by
-at least one of the pins in test_oracle_pins.py.  The mutant is compiled from
+at least one of the pins in test_oracle_pins.py or test_oracle_next.py.  The mutant is compiled from
 a patched copy of oracle/adop_oracle.c into a temporary directory and loaded
 in place of the real oracle for the duration of one check (CPU only)."""
 import os
@@ -7,6 +7,7 @@ import subprocess
 
 import pytest
 
+import tests.test_oracle_next as nxt
 import tests.test_oracle_pins as pins
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -22,13 +23,13 @@ MUTANTS = [
      lambda O: pins.test_microscenes(O, MICRO["S6_two_layers"])),
     ("case2_no_fuzz", "if (Z > behind) return 0.0;", "if (Z > minz) return 0.0;",
      lambda O: pins.test_spatial_gradient_equals_rerender(O, 21, 1)),
-    ("case4_mean", "double Inew = ((double)nq * I + (double)tau[ch]) / (double)(nq + 1);",
-     "double Inew = ((double)nq * I + (double)tau[ch]) / (double)(nq);",
+    ("case4_mean", "double Inew = ((double)nq * I + tau[ch]) / (double)(nq + 1);",
+     "double Inew = ((double)nq * I + tau[ch]) / (double)(nq);",
      lambda O: pins.test_microscenes(O, MICRO["S4b_equal_depth_n3"])),
-    ("case1_background", "double dI = (double)tau[ch] - (double)background[ch];",
-     "double dI = (double)tau[ch];",
+    ("case1_background", "double dI = tau[ch] - (double)background[ch];",
+     "double dI = tau[ch];",
      lambda O: pins.test_microscenes(O, MICRO["S8_background"])),
-    ("dfeat_count", "dfeat[i * c + ch] += g / k;", "dfeat[i * c + ch] += g;",
+    ("dfeat_count", "dfeat[i * c + ch] += g / k * chain;", "dfeat[i * c + ch] += g * chain;",
      lambda O: pins.test_feature_gradient_finite_difference(O)),
     ("visible_gate", "if (!visible && !(flags & ORACLE_SPATIAL_ALL)) continue;",
      "if (0) continue;",
@@ -52,6 +53,20 @@ MUTANTS = [
      lambda O: pins.test_forward_matches_brute_force(O, 1, 0.01)),
     ("bounds_closed", "fx < (float)wl && fy >= 0.0f && fy < (float)hl", "fx <= (float)wl && fy >= 0.0f && fy <= (float)hl",
      lambda O: pins.test_rounding_ties_and_bounds(O)),
+    ("cull_sign", "if (opt->flags & ORACLE_CULL_BACKFACE) return d < 0.0f;",
+     "if (opt->flags & ORACLE_CULL_BACKFACE) return d > 0.0f;",
+     lambda O: nxt.test_normal_culling_equals_rendering_the_kept_subset(O, "backface")),
+    ("cull_normal_untransformed", "float m2 = fmaf(R[6], nv[0], fmaf(R[7], nv[1], R[8] * nv[2]));",
+     "float m2 = nv[2];",
+     lambda O: nxt.test_normal_culling_equals_rendering_the_kept_subset(O, "printed")),
+    ("log_chain", "double chain = (flags & ORACLE_LOG_FEATURES) ? tau[ch] : 1.0;", "double chain = 1.0;",
+     lambda O: nxt.test_log_features_gradient_finite_difference(O)),
+    ("discard_layer_scale", "float lhs = ldexpf(s0, -l) * opt->gamma;", "float lhs = s0 * opt->gamma;",
+     lambda O: nxt.test_discard_equals_rendering_each_layers_kept_subset(O)),
+    ("discard_no_sqrt", "float rhs = sqrtf(1.0f - opt->beta[i]);", "float rhs = 1.0f - opt->beta[i];",
+     lambda O: nxt.test_discard_equals_rendering_each_layers_kept_subset(O)),
+    ("knn_third", "radius[i] = sqrtf(best[3]);", "radius[i] = sqrtf(best[2]);",
+     lambda O: nxt.test_knn_radius_against_kdtree(O)),
 ]
 
 
