@@ -197,6 +197,11 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-batch", type=int, default=4)
     ap.add_argument("--serve-budget-gib", type=int, default=96)
+    ap.add_argument("--discard", action="store_true",
+                    help="stochastic point discarding (gamma 1.5, 4-NN radius, seeded beta)")
+    ap.add_argument("--cull", default="", choices=["", "backface", "printed"],
+                    help="normal culling with seeded random unit normals")
+    ap.add_argument("--log-features", action="store_true", help="features are logarithmic descriptors")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -240,6 +245,11 @@ def main():
     C = s.c
     target = torch.from_numpy(synth.target_values(adop.views_layout(s.cams, s.layers)[0] * C)).to(dev)
 
+    flags = ((adop.FLAG_DISCARD if args.discard else 0) | (adop.FLAG_LOG_FEATURES if args.log_features else 0) |
+             {"": 0, "backface": adop.FLAG_CULL_BACKFACE, "printed": adop.FLAG_CULL_PRINTED}[args.cull])
+    options = [o for o, on in (("discard", args.discard), ("log_features", args.log_features),
+                               (f"cull_{args.cull}", bool(args.cull))) if on]
+
     def run(dtype, steps, warmup, timing):
         code = adop.DTYPES[dtype]
         raw, _ = synth.storage(s.feat, dtype)
@@ -251,9 +261,19 @@ def main():
         scene = adop.Scene.prepare(ctx, pos, feat, code)
         del pos, feat
         torch.cuda.synchronize()
+        pre = {}
+        if args.cull:
+            scene.set_normals(ctx, torch.from_numpy(synth.unit_vectors(s.n, 4001)).to(dev))
+        if args.discard:
+            scene.beta = scene.gather(ctx, torch.from_numpy(synth.uniform01(s.n, 4002)).to(dev))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            scene.radius = adop.knn_radius(ctx, scene)
+            torch.cuda.synchronize()
+            pre["knn_radius_s"] = round(time.perf_counter() - t0, 3)
         frame = adop.Frame(s.cams, s.layers, C, dev)
         ws = ctx.workspace(C, V, frame.pixels)
-        adop.render_forward(ctx, scene, frame.cams, s.layers, alpha=s.alpha, frame=frame, workspace=ws)
+        adop.render_forward(ctx, scene, frame.cams, s.layers, alpha=s.alpha, frame=frame, workspace=ws, flags=flags)
         G = l1_grad(frame, target)
         out = (torch.empty((scene.n, C), dtype=torch.float32, device=dev),
                torch.empty((3, scene.n), dtype=torch.float32, device=dev),
@@ -261,8 +281,9 @@ def main():
                torch.empty((V, 9), dtype=torch.float64, device=dev))
 
         def step():
-            adop.render_forward(ctx, scene, frame.cams, s.layers, alpha=s.alpha, frame=frame, workspace=ws)
-            adop.render_backward(ctx, scene, frame, G, alpha=s.alpha, out=out, workspace=ws)
+            adop.render_forward(ctx, scene, frame.cams, s.layers, alpha=s.alpha, frame=frame, workspace=ws,
+                                flags=flags)
+            adop.render_backward(ctx, scene, frame, G, alpha=s.alpha, out=out, workspace=ws, flags=flags)
 
         for _ in range(warmup):
             step()
@@ -287,7 +308,8 @@ def main():
         phi = float(nz.float().mean().item())
         res = dict(ms=ms, kern=kern, phi=phi, pixels=frame.pixels,
                    s=4 if dtype == "f32" else 2,
-                   coverage=float((frame.counts > 0).float().mean().item()))
+                   coverage=float((frame.counts > 0).float().mean().item()),
+                   blends=int(frame.counts.sum().item()), pre=pre)
         del scene, frame, G, out
         torch.cuda.empty_cache()
         return res
@@ -301,7 +323,7 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["avg_ms"])
     achieved = ab[dom] / (kern[dom]["avg_ms"] * 1e-3) / 1e9
     step_bytes = sum(ab.values())
-    rec = recorded_counters(dom, s.name, args.dtype)
+    rec = recorded_counters(dom, s.name, args.dtype) if not options else None
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": int(rec["bytes_per_launch"]) if rec and "bytes_per_launch" in rec else None,
@@ -321,7 +343,7 @@ def main():
         variants[vd] = {"value": n * V / (rv["ms"] * 1e-3), "ms_per_step": round(rv["ms"], 4),
                         "step_frac_of_hbm_roofline": round(sum(abv.values()) / (rv["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     cpu = None
-    if not args.no_cpu and V == 1:
+    if not args.no_cpu and V == 1 and not options:
         log(f"cpu baseline on {args.cpu_sample} points")
         cpu = cpu_baseline(s, args.cpu_sample)
     line = {
@@ -350,6 +372,9 @@ def main():
         "roofline": roofline,
         "alu_issue": alu_issue,
         "cpu_baseline": cpu,
+        "options": options,
+        "blends": r["blends"],
+        "preprocess": r["pre"],
         "precision_variants": variants,
     }
     print(json.dumps(line), flush=True)

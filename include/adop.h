@@ -63,6 +63,25 @@ typedef int32_t adop_dtype;
 /* render flags */
 #define ADOP_FLAG_SPATIAL_ALL 1u  /* spatial gradient for every in-bounds point,
                                      not only points in the blend set */
+/* Normal culling (Eq. normalculling) needs scene normals.  With n the point's
+ * normal and x_c = R x + t, the sign of d = (R n) . x_c decides (the printed
+ * division by |x_c| > 0 does not change it), in FP32 with the nesting of the
+ * projection: m_k = fma(R[3k], nx, fma(R[3k+1], ny, R[3k+2] nz)),
+ * d = fma(m_0, X, fma(m_1, Y, m_2 Z)).  A culled point takes no part in any
+ * pass of that view.  At most one of the two flags may be set. */
+#define ADOP_FLAG_CULL_BACKFACE 2u   /* keep d < 0: the normal faces the camera */
+#define ADOP_FLAG_CULL_PRINTED 4u    /* keep d > 0: the inequality as printed */
+/* Logarithmic descriptors (Sec. 4, network architecture): the stored
+ * features are log values; every pass uses exp(feat) and dfeat is the
+ * gradient with respect to the stored (log) values. */
+#define ADOP_FLAG_LOG_FEATURES 8u
+/* Stochastic point discarding (Eq. discard) needs scene radius and beta: a
+ * point takes part in layer l only if, in FP32,
+ *   (((fx * radius) / Z) * 2^-l) * gamma > sqrt(1 - beta)
+ * i.e. r_screen / sqrt(1 - beta) > 1 / gamma with the world radius (the
+ * distance to the 4th-nearest point, adop_knn_radius) projected to layer-l
+ * pixels; gamma = params->gamma. */
+#define ADOP_FLAG_DISCARD 16u
 
 /* Camera: pinhole with Brown-Conrady radial (k1,k2,k3) and tangential
  * (p1,p2) distortion, world->camera pose x_c = R x + t (R row-major, OpenCV
@@ -91,6 +110,7 @@ typedef struct adop_render_params {
     float alpha;               /* fuzzy depth test z <= (1+alpha) min_z (Eq. depthtest); >= 0 */
     uint32_t flags;            /* ADOP_FLAG_* */
     const float* background;   /* host, [channels] colour of empty pixels; NULL = zeros */
+    float gamma;               /* ADOP_FLAG_DISCARD: > 0 (the paper uses 1.5) */
 } adop_render_params;
 
 /* A prepared scene (see adop_scene_prepare).  The SoA position planes and the
@@ -106,6 +126,11 @@ typedef struct adop_scene {
     const float* z;            /* device [n] */
     const void* feat;          /* device [n][C] of dtype, 16-byte aligned */
     const int32_t* orig_index; /* device [n] */
+    const float* nx;           /* device [n] normals (ADOP_FLAG_CULL_*), else may be NULL */
+    const float* ny;
+    const float* nz;
+    const float* radius;       /* device [n] world radius (ADOP_FLAG_DISCARD), else may be NULL */
+    const float* beta;         /* device [n] U[0,1) per point (ADOP_FLAG_DISCARD), else may be NULL */
 } adop_scene;
 
 /* Rendered frame buffers (device, caller-owned), layout in the file comment. */
@@ -166,6 +191,24 @@ adop_status adop_scene_prepare(adop_context* ctx, const float* pos, const void* 
                                int32_t block, uint64_t seed,
                                float* x, float* y, float* z, void* feat_out,
                                int32_t* orig_index, void* stream);
+
+/* Gather per-point values of the caller's order into the prepared order:
+ * dst[k * n + i] = src[orig_index[i] * components + k] for k < components
+ * (so normals [n][3] become the planes nx, ny, nz).  Device pointers, FP32,
+ * 1 <= components <= 4.  Asynchronous on `stream`. */
+adop_status adop_scene_gather(adop_context* ctx, const float* src, int32_t components, int64_t n,
+                              const int32_t* orig_index, float* dst, void* stream);
+
+/* World radius of stochastic discarding (Sec. 3.1, "Stochastic Point
+ * Discarding"): radius[i] = distance from point i to its 4th-nearest other
+ * point, over the SoA positions x, y, z (any order; duplicates count at
+ * distance 0).  Squared distances are evaluated in FP32 as
+ * fma(dx, dx, fma(dy, dy, dz dz)) with d = p_j - p_i and the radius is the
+ * correctly rounded square root of the 4th smallest, so the result is exact
+ * for the stated formula.  n >= 5.  Allocates and frees temporary device
+ * memory (about 40 bytes per point); synchronises `stream` before returning. */
+adop_status adop_knn_radius(adop_context* ctx, const float* x, const float* y, const float* z,
+                            int64_t n, float* radius, void* stream);
 
 /* ---------------------------------------------------------- rendering */
 /* Forward pass (Eqs. render, round, boundscheck, depthtest, blend): the

@@ -46,13 +46,15 @@ class Camera(ct.Structure):
 
 class RenderParams(ct.Structure):
     _fields_ = [("layers", ct.c_int32), ("alpha", ct.c_float), ("flags", ct.c_uint32),
-                ("background", ct.c_void_p)]
+                ("background", ct.c_void_p), ("gamma", ct.c_float)]
 
 
 class SceneDesc(ct.Structure):
     _fields_ = [("n", ct.c_int64), ("channels", ct.c_int32), ("dtype", ct.c_int32),
                 ("x", ct.c_void_p), ("y", ct.c_void_p), ("z", ct.c_void_p),
-                ("feat", ct.c_void_p), ("orig_index", ct.c_void_p)]
+                ("feat", ct.c_void_p), ("orig_index", ct.c_void_p),
+                ("nx", ct.c_void_p), ("ny", ct.c_void_p), ("nz", ct.c_void_p),
+                ("radius", ct.c_void_p), ("beta", ct.c_void_p)]
 
 
 class FrameDesc(ct.Structure):
@@ -89,6 +91,10 @@ def lib():
         L.adop_feature_bytes.argtypes = [I64, I32, I32]
         L.adop_scene_prepare.restype = S
         L.adop_scene_prepare.argtypes = [P, P, P, I64, I32, I32, I32, ct.c_uint64, P, P, P, P, P, P]
+        L.adop_scene_gather.restype = S
+        L.adop_scene_gather.argtypes = [P, P, I32, I64, P, P, P]
+        L.adop_knn_radius.restype = S
+        L.adop_knn_radius.argtypes = [P, P, P, P, I64, P, P]
         L.adop_render_forward.restype = S
         L.adop_render_forward.argtypes = [P, P, P, I32, P, P, P, ct.c_size_t, P]
         L.adop_render_backward.restype = S
@@ -111,7 +117,8 @@ def lib():
 
 EXPORTS = ["adop_version", "adop_status_string", "adop_context_create", "adop_context_destroy",
            "adop_last_error", "adop_views_layout", "adop_workspace_bytes", "adop_feature_bytes",
-           "adop_scene_prepare", "adop_render_forward", "adop_render_backward",
+           "adop_scene_prepare", "adop_scene_gather", "adop_knn_radius",
+           "adop_render_forward", "adop_render_backward",
            "adop_forward_graph_create", "adop_forward_graph_launch", "adop_graph_destroy",
            "adop_timing_enable", "adop_timing_read", "adop_timing_kernel_name"]
 TIMING_KERNELS = 7
@@ -213,6 +220,9 @@ class Scene:
     def __init__(self, x, y, z, feat, orig, dtype: int):
         self.x, self.y, self.z, self.feat, self.orig = x, y, z, feat, orig
         self.dtype = dtype
+        self.normals = None    # [3, n] planes (normal culling)
+        self.radius = None     # [n] world radius (stochastic discarding)
+        self.beta = None       # [n] U[0,1) per point (stochastic discarding)
 
     @property
     def n(self) -> int:
@@ -223,8 +233,33 @@ class Scene:
         return int(self.feat.shape[1])
 
     def desc(self) -> SceneDesc:
+        nrm = self.normals
         return SceneDesc(self.n, self.channels, self.dtype, _ptr(self.x), _ptr(self.y), _ptr(self.z),
-                         _ptr(self.feat), _ptr(self.orig))
+                         _ptr(self.feat), _ptr(self.orig),
+                         _ptr(nrm[0]) if nrm is not None else None, _ptr(nrm[1]) if nrm is not None else None,
+                         _ptr(nrm[2]) if nrm is not None else None, _ptr(self.radius), _ptr(self.beta))
+
+    def gather(self, ctx: "Context", values: torch.Tensor, stream=None) -> torch.Tensor:
+        """Per-point values in the caller's order ([n] or [n, k], k <= 4,
+        FP32 device) -> planes [k, n] (or [n]) in the prepared order."""
+        v = values.contiguous()
+        assert v.is_cuda and v.dtype == torch.float32 and v.shape[0] == self.n
+        k = 1 if v.dim() == 1 else int(v.shape[1])
+        out = torch.empty((k, self.n), dtype=torch.float32, device=v.device)
+        st = lib().adop_scene_gather(ctx.handle, _ptr(v), k, self.n, _ptr(self.orig), _ptr(out), _stream(stream))
+        ctx.check(st, "adop_scene_gather")
+        return out[0] if v.dim() == 1 else out
+
+    def set_normals(self, ctx: "Context", normals: torch.Tensor, stream=None):
+        """Normals [n, 3] in the caller's order (normal culling)."""
+        self.normals = self.gather(ctx, normals, stream)
+
+    def set_discard(self, ctx: "Context", beta: torch.Tensor, radius: Optional[torch.Tensor] = None,
+                    stream=None):
+        """Stochastic discarding inputs: beta [n] in the caller's order and
+        the world radius (computed with adop_knn_radius when not given)."""
+        self.beta = self.gather(ctx, beta, stream)
+        self.radius = self.gather(ctx, radius, stream) if radius is not None else knn_radius(ctx, self, stream)
 
     @staticmethod
     def prepare(ctx: Context, pos: torch.Tensor, feat: torch.Tensor, dtype: int = F32,
@@ -257,11 +292,30 @@ class Scene:
                      feat.contiguous(), torch.arange(n, dtype=torch.int32, device=pos.device), dtype)
 
 
-def _params(layers: int, alpha: float, flags: int, background, C: int):
+def knn_radius(ctx: "Context", scene: Scene, stream=None) -> torch.Tensor:
+    """Distance of every point of the scene to its 4th-nearest other point
+    (prepared order)."""
+    out = torch.empty(scene.n, dtype=torch.float32, device=scene.x.device)
+    st = lib().adop_knn_radius(ctx.handle, _ptr(scene.x), _ptr(scene.y), _ptr(scene.z), scene.n, _ptr(out),
+                               _stream(stream))
+    ctx.check(st, "adop_knn_radius")
+    return out
+
+
+FLAG_SPATIAL_ALL = 1
+FLAG_CULL_BACKFACE = 2
+FLAG_CULL_PRINTED = 4
+FLAG_LOG_FEATURES = 8
+FLAG_DISCARD = 16
+GAMMA = 1.5   # the paper's discarding parameter
+
+
+def _params(layers: int, alpha: float, flags: int, background, C: int, gamma: float = GAMMA):
     bg = None
     if background is not None:
         bg = (ct.c_float * C)(*[float(b) for b in np.asarray(background, np.float32).reshape(C)])
-    p = RenderParams(layers, float(np.float32(alpha)), flags, ct.cast(bg, ct.c_void_p) if bg is not None else None)
+    p = RenderParams(layers, float(np.float32(alpha)), flags, ct.cast(bg, ct.c_void_p) if bg is not None else None,
+                     float(np.float32(gamma)))
     return p, bg
 
 
@@ -299,7 +353,7 @@ class Frame:
 
 def render_forward(ctx: Context, scene: Scene, cams, layers: int, alpha: float = 0.01, flags: int = 0,
                    background=None, frame: Optional[Frame] = None, stream=None,
-                   workspace: Optional[torch.Tensor] = None) -> Frame:
+                   workspace: Optional[torch.Tensor] = None, gamma: float = GAMMA) -> Frame:
     C = scene.channels
     if frame is None:
         frame = Frame(cams, layers, C, scene.x.device)
@@ -311,7 +365,7 @@ def render_forward(ctx: Context, scene: Scene, cams, layers: int, alpha: float =
             raise ValueError("cameras, layers or channels do not match the given frame")
         frame.cams = arr
     ws = workspace if workspace is not None else ctx.workspace(C, len(frame.cams), frame.pixels)
-    p, keep = _params(layers, alpha, flags, background, C)
+    p, keep = _params(layers, alpha, flags, background, C, gamma)
     sd = scene.desc()
     fd = frame.desc()
     st = lib().adop_render_forward(ctx.handle, ct.byref(sd), frame.cams, len(frame.cams), ct.byref(p),
@@ -322,7 +376,7 @@ def render_forward(ctx: Context, scene: Scene, cams, layers: int, alpha: float =
 
 def render_backward(ctx: Context, scene: Scene, frame: Frame, grad: torch.Tensor, alpha: float = 0.01,
                     flags: int = 0, background=None, stream=None, out=None,
-                    workspace: Optional[torch.Tensor] = None):
+                    workspace: Optional[torch.Tensor] = None, gamma: float = GAMMA):
     """Returns (dfeat [n,C] f32, dpos [3,n] f32, dpose [V,6] f64, dintr [V,9] f64)."""
     C = scene.channels
     V = len(frame.cams)
@@ -336,7 +390,7 @@ def render_backward(ctx: Context, scene: Scene, frame: Frame, grad: torch.Tensor
                torch.empty((V, 9), dtype=torch.float64, device=dev))
     dfeat, dpos, dpose, dintr = out
     ws = workspace if workspace is not None else ctx.workspace(C, V, frame.pixels)
-    p, keep = _params(frame.layers, alpha, flags, background, C)
+    p, keep = _params(frame.layers, alpha, flags, background, C, gamma)
     sd = scene.desc()
     fd = frame.desc()
     st = lib().adop_render_backward(ctx.handle, ct.byref(sd), frame.cams, V, ct.byref(p), ct.byref(fd),
@@ -351,7 +405,7 @@ class ForwardGraph:
     cameras of the same sizes are staged on every launch."""
 
     def __init__(self, ctx: Context, scene: Scene, cams, layers: int, alpha: float = 0.01, flags: int = 0,
-                 background=None):
+                 background=None, gamma: float = GAMMA):
         self.ctx = ctx
         self.scene = scene
         C = scene.channels
@@ -359,7 +413,7 @@ class ForwardGraph:
         V = len(self.frame.cams)
         need = ctx.workspace_bytes(C, V, self.frame.pixels)
         self.ws = torch.empty(need, dtype=torch.uint8, device=scene.x.device)
-        p, keep = _params(layers, alpha, flags, background, C)
+        p, keep = _params(layers, alpha, flags, background, C, gamma)
         sd = scene.desc()
         fd = self.frame.desc()
         h = ct.c_void_p()

@@ -17,7 +17,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libadop.so")
 ARCH = os.environ.get("ADOP_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "render.hip", "scene.hip"]
+SOURCES = ["api.cpp", "render.hip", "render_c1.hip", "render_c2.hip", "render_c3.hip", "render_c4.hip",
+           "scene.hip", "knn.hip"]
 
 COMMON = [
     "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
@@ -45,9 +46,11 @@ def _compile(src: str, verbose: bool, defines=(), build_dir=BUILD) -> str:
     return obj
 
 
-def build(verbose: bool = False, jobs: int = 3, defines=(), out: str = LIB, build_dir: str = BUILD) -> str:
+def build(verbose: bool = False, jobs: int = 0, defines=(), out: str = LIB, build_dir: str = BUILD) -> str:
     """Compile the sources (optionally with tuning macros `defines`, e.g.
     "ADOP_MAX_GROUPS=0") and link `out`."""
+    if jobs <= 0:
+        jobs = max(1, min(len(SOURCES), os.cpu_count() or 1))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose, defines, build_dir), SOURCES))
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", out + ".tmp", *objs]
@@ -59,9 +62,9 @@ def build(verbose: bool = False, jobs: int = 3, defines=(), out: str = LIB, buil
 
 
 def disassemble(out_path: str) -> None:
-    """Write the gfx950 ISA of render.hip (for inspection of our own code)."""
+    """Write the gfx950 ISA of the 1..4-channel kernels (for inspection of our own code)."""
     cmd = [hipcc(), "-x", "hip", *COMMON, "--cuda-device-only", "-S",
-           os.path.join(CSRC, "render.hip"), "-o", out_path]
+           os.path.join(CSRC, "render_c1.hip"), "-o", out_path]
     subprocess.run(cmd, check=True)
 
 

@@ -171,7 +171,20 @@ adop_status check_common(adop_context* ctx, const adop_scene* scene, const adop_
         return fail(ctx, ADOP_E_INVALID, "alpha must be finite and >= 0");
     s = check_cameras(ctx, cams, V, params->layers, vmax);
     if (s) return s;
-    if (params->flags & ~ADOP_FLAG_SPATIAL_ALL) return fail(ctx, ADOP_E_INVALID, "unknown flags 0x%x", params->flags);
+    const uint32_t known = ADOP_FLAG_SPATIAL_ALL | ADOP_FLAG_CULL_BACKFACE | ADOP_FLAG_CULL_PRINTED |
+                           ADOP_FLAG_LOG_FEATURES | ADOP_FLAG_DISCARD;
+    if (params->flags & ~known) return fail(ctx, ADOP_E_INVALID, "unknown flags 0x%x", params->flags);
+    if ((params->flags & ADOP_FLAG_CULL_BACKFACE) && (params->flags & ADOP_FLAG_CULL_PRINTED))
+        return fail(ctx, ADOP_E_INVALID, "at most one of the normal-culling flags may be set");
+    if ((params->flags & (ADOP_FLAG_CULL_BACKFACE | ADOP_FLAG_CULL_PRINTED)) && scene->n > 0 &&
+        (!scene->nx || !scene->ny || !scene->nz))
+        return fail(ctx, ADOP_E_INVALID, "normal culling needs scene normals nx, ny, nz");
+    if (params->flags & ADOP_FLAG_DISCARD) {
+        if (scene->n > 0 && (!scene->radius || !scene->beta))
+            return fail(ctx, ADOP_E_INVALID, "stochastic discarding needs scene radius and beta");
+        if (!(params->gamma > 0.0f) || !std::isfinite(params->gamma))
+            return fail(ctx, ADOP_E_INVALID, "stochastic discarding needs a finite gamma > 0");
+    }
     if (!frame || !frame->images || !frame->keys || !frame->counts) return fail(ctx, ADOP_E_INVALID, "frame has a NULL buffer");
     layout(cams, V, params->layers, total, nullptr);
     if (frame->pixels != *total)
@@ -246,6 +259,16 @@ adop::Timer timer_of(adop_context* ctx) {
     return t;
 }
 
+adop::PointOpts point_opts(const adop_scene* scene, const adop_render_params* params) {
+    adop::PointOpts o;
+    o.flags = params->flags & (ADOP_FLAG_CULL_BACKFACE | ADOP_FLAG_CULL_PRINTED | ADOP_FLAG_LOG_FEATURES |
+                               ADOP_FLAG_DISCARD);
+    o.gamma = (params->flags & ADOP_FLAG_DISCARD) ? params->gamma : 0.0f;
+    o.nx = scene->nx; o.ny = scene->ny; o.nz = scene->nz;
+    o.radius = scene->radius; o.beta = scene->beta;
+    return o;
+}
+
 adop::FwdArgs fwd_args(adop_context* ctx, const adop_scene* scene, const adop_camera* cams, int32_t V,
                        const adop_render_params* params, const adop_frame* frame, void* ws, int64_t total) {
     adop::FwdArgs a;
@@ -267,6 +290,7 @@ adop::FwdArgs fwd_args(adop_context* ctx, const adop_scene* scene, const adop_ca
     a.sums = reinterpret_cast<float*>(static_cast<unsigned char*>(ws) + views_region(V));
     a.images = frame->images;
     a.background = params->background;
+    a.opts = point_opts(scene, params);
     a.timer = timer_of(ctx);
     return a;
 }
@@ -408,6 +432,29 @@ adop_status adop_scene_prepare(adop_context* ctx, const float* pos, const void* 
     return ADOP_OK;
 }
 
+adop_status adop_scene_gather(adop_context* ctx, const float* src, int32_t components, int64_t n,
+                              const int32_t* orig_index, float* dst, void* stream) {
+    if (!ctx) return ADOP_E_INVALID;
+    ctx->err.clear();
+    if (n < 0 || n > 0x7fffffffLL) return fail(ctx, ADOP_E_INVALID, "n=%lld outside [0, 2^31-1]", (long long)n);
+    if (components < 1 || components > 4) return fail(ctx, ADOP_E_INVALID, "components=%d outside [1,4]", components);
+    if (n > 0 && (!src || !orig_index || !dst)) return fail(ctx, ADOP_E_INVALID, "NULL pointer");
+    hipError_t e = adop::scene_gather(src, components, n, orig_index, dst, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "scene_gather");
+    return ADOP_OK;
+}
+
+adop_status adop_knn_radius(adop_context* ctx, const float* x, const float* y, const float* z, int64_t n,
+                            float* radius, void* stream) {
+    if (!ctx) return ADOP_E_INVALID;
+    ctx->err.clear();
+    if (n < 5 || n > 0x7fffffffLL) return fail(ctx, ADOP_E_INVALID, "n=%lld outside [5, 2^31-1]", (long long)n);
+    if (!x || !y || !z || !radius) return fail(ctx, ADOP_E_INVALID, "NULL pointer");
+    hipError_t e = adop::knn_radius(x, y, z, n, radius, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "knn_radius");
+    return ADOP_OK;
+}
+
 adop_status adop_render_forward(adop_context* ctx, const adop_scene* scene, const adop_camera* cams, int32_t V,
                                 const adop_render_params* params, const adop_frame* frame, void* workspace,
                                 size_t workspace_bytes_, void* stream) {
@@ -464,6 +511,7 @@ adop_status adop_render_backward(adop_context* ctx, const adop_scene* scene, con
     a.dpose = dpose;
     a.dintr = dintr;
     a.background = params->background;
+    a.opts = point_opts(scene, params);
     a.timer = timer_of(ctx);
     hipError_t e = adop::launch_backward(a, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "backward launch");

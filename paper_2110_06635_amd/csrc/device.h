@@ -11,6 +11,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include "launch.h"
 
 namespace adop {
 
@@ -132,6 +133,53 @@ template <typename CamT>
 __device__ __forceinline__ bool layer_pixel(const CamT& c, bool ok, int l, float u0, float v0,
                                             int& px, int& py, uint32_t& pix) {
     return layer_pixel_at(ok, l, c.lw[l], c.lh[l], c.base[l], u0, v0, px, py, pix);
+}
+
+// Correctly rounded square root of a binary32 value.  The hardware square
+// root is within one unit in the last place; the neighbour that is the
+// correctly rounded result is found by comparing x with the squared
+// midpoints between neighbouring floats, which are exact in binary64
+// (25-bit midpoints, 50-bit squares); ties go to the even neighbour.
+__device__ __forceinline__ float sqrt_rn(float x) {
+    if (!(x > 0.0f) || !__builtin_isfinite(x)) return __builtin_sqrtf(x);
+    float y = __builtin_sqrtf(x);
+    const double xd = (double)x;
+    for (int it = 0; it < 2; ++it) {
+        const uint32_t b = __float_as_uint(y);
+        const float up = __uint_as_float(b + 1u), dn = __uint_as_float(b - 1u);
+        const double mh = 0.5 * ((double)y + (double)up), ml = 0.5 * ((double)dn + (double)y);
+        const double h2 = mh * mh, l2 = ml * ml;
+        if (xd > h2 || (xd == h2 && (b & 1u))) y = up;
+        else if (xd < l2 || (xd == l2 && (b & 1u))) y = dn;
+        else break;
+    }
+    return y;
+}
+
+// Eq. normalculling for point i (see kOptCull*): the sign of (R n) . x_c in
+// FP32 with the nesting of the projection.
+template <typename CamT>
+__device__ __forceinline__ bool normal_kept(const PointOpts& o, const CamT& c, const Proj& p, int64_t i) {
+    if (!(o.flags & (kOptCullBack | kOptCullPrinted))) return true;
+    const float nx = o.nx[i], ny = o.ny[i], nz = o.nz[i];
+    const float m0 = __fmaf_rn(c.R[0], nx, __fmaf_rn(c.R[1], ny, __fmul_rn(c.R[2], nz)));
+    const float m1 = __fmaf_rn(c.R[3], nx, __fmaf_rn(c.R[4], ny, __fmul_rn(c.R[5], nz)));
+    const float m2 = __fmaf_rn(c.R[6], nx, __fmaf_rn(c.R[7], ny, __fmul_rn(c.R[8], nz)));
+    const float d = __fmaf_rn(m0, p.X, __fmaf_rn(m1, p.Y, __fmul_rn(m2, p.Z)));
+    return (o.flags & kOptCullBack) ? d < 0.0f : d > 0.0f;
+}
+
+// Eq. discard for point i: bit l set when the point takes part in layer l,
+// i.e. ((fx r / Z) 2^-l) gamma > sqrt(1 - beta) in FP32 (all bits without
+// discarding).
+template <typename CamT>
+__device__ __forceinline__ uint32_t discard_mask(const PointOpts& o, const CamT& c, const Proj& p, int64_t i, int L) {
+    if (!(o.flags & kOptDiscard)) return 0xffu;
+    const float s0 = __fdiv_rn(__fmul_rn(c.fx, o.radius[i]), p.Z);
+    const float rhs = sqrt_rn(__fsub_rn(1.0f, o.beta[i]));
+    uint32_t m = 0;
+    for (int l = 0; l < L; ++l) m |= (uint32_t)(__fmul_rn(__fmul_rn(s0, layer_scale(l)), o.gamma) > rhs) << l;
+    return m;
 }
 
 // ----------------------------------------------------------------------------

@@ -25,6 +25,16 @@ struct Timer {
     }
 };
 
+// Optional per-point inputs and switches of the point kernels (normal
+// culling, logarithmic features, stochastic discarding).
+struct PointOpts {
+    uint32_t flags;        // kOpt* bits
+    float gamma;
+    const float *nx, *ny, *nz;
+    const float *radius, *beta;
+};
+constexpr uint32_t kOptCullBack = 2u, kOptCullPrinted = 4u, kOptLog = 8u, kOptDiscard = 16u;
+
 struct FwdArgs {
     int dtype, C, V, L, cus;
     int64_t n, pixels, max_layer_pixels;
@@ -38,6 +48,7 @@ struct FwdArgs {
     float* sums;       // workspace [pixels][C]
     float* images;
     const float* background;   // host [C] or null
+    PointOpts opts;
     Timer timer;
 };
 
@@ -53,6 +64,7 @@ struct BwdArgs {
     const int32_t* counts;
     const float* images;
     const float* grad;
+    PointOpts opts;
     float* pack;       // workspace [pixels][stride]
     double* partials;  // workspace [groups][V][16]
     float* dfeat;
@@ -80,5 +92,9 @@ struct PrepArgs {
 };
 // Returns hipSuccess or the first HIP error; allocates temporaries.
 hipError_t scene_prepare(const PrepArgs& a, hipStream_t st);
+// dst[k * n + i] = src[orig[i] * comp + k]
+hipError_t scene_gather(const float* src, int comp, int64_t n, const int32_t* orig, float* dst, hipStream_t st);
+// distance of every point to its 4th-nearest other point (allocates; synchronises st)
+hipError_t knn_radius(const float* x, const float* y, const float* z, int64_t n, float* radius, hipStream_t st);
 
 }  // namespace adop

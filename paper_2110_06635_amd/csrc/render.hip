@@ -1,1091 +1,59 @@
-// HIP kernels of the one-pixel point rasterizer (ADOP Sec. 3.1) for gfx950.
-//
-// Forward (three passes over the points, as in "Implementation Details"):
-//   k_clear      keys := empty, counts := 0, sums := 0
-//   k_depth      project every point into every view and layer, 64-bit
-//                atomic minimum of (depth bits << 32 | original index)
-//   k_accum      fuzzy depth test z <= (1+alpha) min_z (Eq. depthtest),
-//                FP32 sums of the features and an integer count
-//   k_normalize  mean of the blend set or the background (Eq. blend)
-// Backward:
-//   k_pack       per-pixel record {G, <G,I>, min_z, n} for the gathers
-//   k_backward   re-render every point (the blend sets are not stored),
-//                feature gradient, approximate spatial gradient (Eqs. induce,
-//                gradp, spatialderiv), chain to positions, pose (Eq. tangent)
-//                and intrinsics; per-point terms in FP32, pose/intrinsics
-//                sums in FP64 with a fixed reduction order
-//   k_reduce     fixed-order FP64 sum of the per-workgroup partials
-//
-// Every workgroup of a point kernel owns one contiguous range of the
-// Morton-ordered points (a compact region of space).  The depth and
-// accumulation passes keep a workgroup-private direct-mapped table in LDS
-// (pixel -> minimum key, or pixel -> feature sums and count) for the whole
-// range and write it to global memory with atomics at the end; a pixel whose
-// slot is taken goes straight to the global atomics.  Inside a wave, lanes
-// that hit one pixel are combined first (DPP) so one lane updates for them.
-#include "device.h"
-#include "launch.h"
+// Channel-independent kernels of the rasterizer (clear, depth pass, FP64
+// reduction) and the dispatch of render calls to the channel-count groups
+// compiled in render_c1.hip .. render_c4.hip.
+#define ADOP_RENDER_BASE 1
+#include "render_impl.h"
 
 namespace adop {
 
-#ifndef ADOP_MAX_GROUPS
-#define ADOP_MAX_GROUPS 6
-#endif
-#ifndef ADOP_MIN_GROUP
-#define ADOP_MIN_GROUP 3
-#endif
-#ifndef ADOP_ACC_BITS4
-#define ADOP_ACC_BITS4 9
-#endif
-#ifndef ADOP_DEPTH_BITS
-#define ADOP_DEPTH_BITS 12
-#endif
-#ifndef ADOP_DEPTH_WAVEMIN
-#define ADOP_DEPTH_WAVEMIN 1
-#endif
-// ADOP_DEPTH_TABLE 1: LDS table per workgroup; 0 (default, faster on the
-// benchmark scene): read the global keys of all layers first, then compare
-// and issue the (rare) atomic minimum
-#ifndef ADOP_DEPTH_TABLE
-#define ADOP_DEPTH_TABLE 0
-#endif
-// ADOP_ACC_TABLE 1: LDS table per workgroup; 0: wave groups go straight to
-// global atomics
-#ifndef ADOP_ACC_TABLE
-#define ADOP_ACC_TABLE 1
-#endif
-// ADOP_BWD_HOIST 1: the backward gathers every layer's min_z before the
-// per-layer neighbour work (one round trip instead of one per layer)
-#ifndef ADOP_BWD_HOIST
-#define ADOP_BWD_HOIST 1
-#endif
-// minimum waves per SIMD the point kernels are compiled for (bounds their
-// register use); 0 leaves the choice to the compiler
-#ifndef ADOP_DEPTH_WPE
-#define ADOP_DEPTH_WPE 0
-#endif
-#ifndef ADOP_ACCUM_WPE
-#define ADOP_ACCUM_WPE 0
-#endif
-#ifndef ADOP_BWD_WPE
-#define ADOP_BWD_WPE 0
-#endif
-#define ADOP_WPE_ATTR(n) __attribute__((amdgpu_waves_per_eu((n) > 0 ? (n) : 1)))
-// ADOP_ACC_WCACHE 1: per-wave register cache of 64 pixel sums in front of
-// the workgroup table
-#ifndef ADOP_ACC_WCACHE
-#define ADOP_ACC_WCACHE 1
-#endif
-// ADOP_DEPTH_RUNS 1: the same for the depth pass (segmented minima)
-#ifndef ADOP_DEPTH_RUNS
-#define ADOP_DEPTH_RUNS 1
-#endif
-// chunks between write-outs of the accumulation's workgroup table (0: only
-// at the end of the workgroup's range)
-#ifndef ADOP_ACC_WINDOW
-#define ADOP_ACC_WINDOW 0
-#endif
-// ADOP_ACC_RUNS 1: a wave whose passing points fall into several pixels
-// sums runs of equal pixels with a segmented DPP scan instead of grouping
-#ifndef ADOP_ACC_RUNS
-#define ADOP_ACC_RUNS 1
-#endif
-#ifndef ADOP_PPL4
-#define ADOP_PPL4 4
-#endif
-
-// ---------------------------------------------------------------------------
-// forward
-// ---------------------------------------------------------------------------
-
-__global__ void __launch_bounds__(256) k_clear(uint64_t* __restrict__ keys, int32_t* __restrict__ counts,
-                                               float* __restrict__ sums, int64_t pixels, int64_t nsum) {
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < pixels; i += stride) {
-        keys[i] = ~0ull;
-        counts[i] = 0;
-    }
-    float4* s4 = reinterpret_cast<float4*>(sums);
-    int64_t n4 = nsum / 4;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride)
-        s4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int64_t i = n4 * 4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nsum; i += stride)
-        sums[i] = 0.f;
-}
-
-// ---- depth pass -----------------------------------------------------------
-constexpr int kDepthBits = ADOP_DEPTH_BITS;
-constexpr int kDepthH = 1 << kDepthBits;
-
-struct DepthTable {
-    uint32_t key[kDepthH];
-    uint64_t val[kDepthH];
-};
-
-__device__ __forceinline__ void global_min(uint64_t* __restrict__ gkeys, uint32_t pix, uint64_t k) {
-    uint64_t cur = load_relaxed_u64(gkeys + pix);
-    if (k < cur) atomic_min_u64(gkeys + pix, k);
-}
-
-// Lower the pixel's minimum to k: read first, update only when it would
-// lower the value (keys only decrease, so a stale read can only let an
-// unnecessary atomic through).
-__device__ __forceinline__ void table_min(DepthTable& t, uint64_t* __restrict__ gkeys, uint32_t pix, uint64_t k) {
-    int slot = table_slot2<kDepthBits>(t.key, pix);
-    if (slot < 0) {
-        global_min(gkeys, pix, k);
-        return;
-    }
-    uint64_t cur = __hip_atomic_load(&t.val[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (k < cur) __hip_atomic_fetch_min(&t.val[slot], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-__device__ __forceinline__ void depth_update(bool in, uint32_t pix, uint64_t key, DepthTable& t,
-                                             uint64_t* __restrict__ gkeys) {
-#if ADOP_DEPTH_WAVEMIN
-    uint64_t m = ballot(in);
-    if (m == 0) return;
-    int leader = __builtin_ctzll(m);
-    uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pix, leader);
-    if (ballot(in && pix != p0) == 0) {
-        uint64_t k = wave_min_u64(in ? key : ~0ull);
-        if (lane_id() == leader) table_min(t, gkeys, p0, k);
-        return;
-    }
-#endif
-    if (in) table_min(t, gkeys, pix, key);
-}
-
-__device__ __forceinline__ void depth_table_clear(DepthTable& t) {
-    for (int j = threadIdx.x; j < kDepthH; j += blockDim.x) {
-        t.key[j] = kEmptySlot;
-        t.val[j] = ~0ull;
-    }
-}
-
-__device__ __forceinline__ void depth_table_flush(DepthTable& t, uint64_t* __restrict__ gkeys) {
-    for (int j = threadIdx.x; j < kDepthH; j += blockDim.x) {
-        uint32_t k = t.key[j];
-        if (k != kEmptySlot) global_min(gkeys, k, t.val[j]);
-    }
-}
-
-__device__ __forceinline__ void depth_point(const Cam& c, int L, bool live, float x, float y, float z, uint32_t oi,
-                                            DepthTable* t, uint64_t* __restrict__ keys) {
-    Proj p = project(c, x, y, z);
-    bool ok = live && p.ok;
-    uint64_t key = ((uint64_t)__float_as_uint(p.Z) << 32) | oi;
-#if ADOP_DEPTH_TABLE
-#pragma unroll
-    for (int l = 0; l < kMaxLayers; ++l) {
-        if (l >= L) break;
-        int px = 0, py = 0;
-        uint32_t pix = 0;
-        bool in = layer_pixel(c, ok, l, p.u0, p.v0, px, py, pix);
-        depth_update(in, pix, key, *t, keys);
-    }
-#else
-    uint32_t pix[kMaxLayers];
-    bool in[kMaxLayers];
-    uint64_t cur[kMaxLayers];
-#pragma unroll
-    for (int l = 0; l < kMaxLayers; ++l) {
-        pix[l] = 0;
-        in[l] = false;
-        cur[l] = 0;
-        if (l < L) {
-            int px = 0, py = 0;
-            in[l] = layer_pixel(c, ok, l, p.u0, p.v0, px, py, pix[l]);
-            cur[l] = load_relaxed_u64(keys + pix[l]);   // pix is valid for every lane
-        }
-    }
-#pragma unroll
-    for (int l = 0; l < kMaxLayers; ++l) {
-        if (l >= L) break;
-        bool want = in[l] && key < cur[l];
-        uint64_t m = ballot(want);
-        if (m == 0) continue;
-        int leader = __builtin_ctzll(m);
-        uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pix[l], leader);
-        if (ballot(want && pix[l] != p0) == 0) {
-            uint64_t k = wave_min_u64(want ? key : ~0ull);
-            if (lane_id() == leader) atomic_min_u64(keys + p0, k);
-        } else {
-#if ADOP_DEPTH_RUNS
-            // several pixels: segmented minima over runs of equal pixels
-            uint64_t k = want ? key : ~0ull;
-            if (run_min_u64(want ? pix[l] : kEmptySlot, kEmptySlot, k)) atomic_min_u64(keys + pix[l], k);
-#else
-            if (want) atomic_min_u64(keys + pix[l], key);
-#endif
-        }
-    }
-#endif
-}
-
-template <bool SINGLE>
-__global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_DEPTH_WPE) k_depth(const float* __restrict__ xs, const float* __restrict__ ys,
-                                               const float* __restrict__ zs, const int32_t* __restrict__ orig,
-                                               int64_t n, const ViewRec* __restrict__ views, int V, int L,
-                                               uint64_t* __restrict__ keys) {
-#if ADOP_DEPTH_TABLE
-    __shared__ DepthTable table;
-    DepthTable* t = &table;
-    depth_table_clear(table);
-    __syncthreads();
-#else
-    DepthTable* t = nullptr;
-#endif
-    const Cam c0 = load_cam(views);
-    RangeMap m = range_map(n, kBlock);
-    // the next chunk's points are loaded while the current one is processed
-    float nx = 0.f, ny = 0.f, nz = 0.f;
-    uint32_t noi = 0;
-    bool nlive = false;
-    auto fetch = [&](int64_t c) {
-        int64_t i = c * kBlock + threadIdx.x;
-        nlive = i < n;
-        if (nlive) {
-            nx = ld_nt(xs + i);
-            ny = ld_nt(ys + i);
-            nz = ld_nt(zs + i);
-            noi = (uint32_t)ld_nt(orig + i);
-        }
-    };
-    if (m.c0 < m.c1) fetch(m.c0);
-    for (int64_t c = m.c0; c < m.c1; ++c) {
-        const bool live = nlive;
-        const float x = nx, y = ny, z = nz;
-        const uint32_t oi = noi;
-        if (c + 1 < m.c1) fetch(c + 1);
-        if (SINGLE) {
-            depth_point(c0, L, live, x, y, z, oi, t, keys);
-        } else {
-            for (int v = 0; v < V; ++v) depth_point(load_cam(views + v), L, live, x, y, z, oi, t, keys);
-        }
-    }
-#if ADOP_DEPTH_TABLE
-    __syncthreads();
-    depth_table_flush(table, keys);
-#endif
-}
-
-// ---- accumulation pass ----------------------------------------------------
-constexpr int kAccWindow = ADOP_ACC_WINDOW;
-constexpr int kMaxGroups = ADOP_MAX_GROUPS;
-constexpr int kMinGroup = ADOP_MIN_GROUP;
-
-template <int C> struct AccTable {
-    static constexpr int bits = !ADOP_ACC_TABLE ? 1 : C <= 4 ? ADOP_ACC_BITS4 : (C <= 8 ? ADOP_ACC_BITS4 - 1 : ADOP_ACC_BITS4 - 2);
-    static constexpr int H = 1 << bits;
-    uint32_t key[H];
-    float sum[C][H];
-    int32_t cnt[H];
-};
-
-template <int C>
-__device__ __forceinline__ void table_add(AccTable<C>& t, float* __restrict__ sums, int32_t* __restrict__ counts,
-                                          uint32_t pix, const float (&s)[C], int32_t k) {
-    int slot = ADOP_ACC_TABLE ? table_slot2<AccTable<C>::bits>(t.key, pix) : -1;
-    if (slot < 0) {
-        float* dst = sums + (uint64_t)pix * C;
-#pragma unroll
-        for (int c = 0; c < C; ++c) atomic_add_f32(dst + c, s[c]);
-        atomic_add_i32(counts + pix, k);
-        return;
-    }
-#pragma unroll
-    for (int c = 0; c < C; ++c)
-        __hip_atomic_fetch_add(&t.sum[c][slot], s[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    __hip_atomic_fetch_add(&t.cnt[slot], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-// Per-wave cache of 64 pixel sums, one slot per lane (direct mapped by a
-// hash of the pixel): a wave's group totals land in a register of the slot's
-// lane; a slot taken by another pixel is first written to the workgroup
-// table.  Consecutive Morton-ordered points hit the same pixels again, so
-// most group totals never touch LDS.
-template <int C> struct WaveCache {
-    uint32_t key;
-    float sum[C];
-    int32_t cnt;
-};
-
-template <int C>
-__device__ __forceinline__ void wcache_init(WaveCache<C>& w) {
-    w.key = kEmptySlot;
-#pragma unroll
-    for (int c = 0; c < C; ++c) w.sum[c] = 0.f;
-    w.cnt = 0;
-}
-
-// s and k are wave-uniform; every lane calls this.
-template <int C>
-__device__ __forceinline__ void wcache_add(WaveCache<C>& w, uint32_t p0, const float (&s)[C], int32_t k,
-                                           AccTable<C>& t, float* __restrict__ sums, int32_t* __restrict__ counts) {
-    const int slot = (int)((p0 * 2654435761u) >> 26);
-    const uint32_t ck = (uint32_t)__builtin_amdgcn_readlane((int)w.key, slot);
-    const bool me = lane_id() == slot;
-    if (ck != p0) {
-        if (me) {
-            if (ck != kEmptySlot) table_add<C>(t, sums, counts, ck, w.sum, w.cnt);
-            w.key = p0;
-#pragma unroll
-            for (int c = 0; c < C; ++c) w.sum[c] = s[c];
-            w.cnt = k;
-        }
-    } else if (me) {
-#pragma unroll
-        for (int c = 0; c < C; ++c) w.sum[c] += s[c];
-        w.cnt += k;
-    }
-}
-
-template <int C>
-__device__ __forceinline__ void wcache_flush(WaveCache<C>& w, AccTable<C>& t, float* __restrict__ sums,
-                                             int32_t* __restrict__ counts) {
-    if (w.key != kEmptySlot) table_add<C>(t, sums, counts, w.key, w.sum, w.cnt);
-    wcache_init<C>(w);
-}
-
-// Lanes whose point passes are grouped by pixel: the first remaining lane's
-// pixel, the ballot of the lanes sharing it, DPP sums; groups smaller than
-// kMinGroup (and lanes left after kMaxGroups) add individually.
-template <int C>
-__device__ __forceinline__ void accum_update(bool pass, uint32_t pix, const float (&f)[C], AccTable<C>& t,
-                                             float* __restrict__ sums, int32_t* __restrict__ counts
-#if ADOP_ACC_WCACHE
-                                             , WaveCache<C>& w
-#endif
-                                             ) {
-    uint64_t rem = ballot(pass);
-    if (rem == 0) return;
-    const int lane = lane_id();
-#if ADOP_ACC_RUNS
-    {
-        // one pixel for every passing lane: one wave sum; otherwise segmented
-        // sums over runs of equal pixels, one update per run
-        const int leader = __builtin_ctzll(rem);
-        const uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pix, leader);
-        const uint64_t mm = ballot(pass && pix == p0);
-        if (mm == rem) {
-            float s[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) s[c] = pass ? f[c] : 0.0f;
-            wave_sum_n<C>(s);
-            const int k = __builtin_popcountll(mm);
-#if ADOP_ACC_WCACHE
-            wcache_add<C>(w, p0, s, k, t, sums, counts);
-#else
-            if (lane == leader) table_add<C>(t, sums, counts, p0, s, k);
-#endif
-            return;
-        }
-        float v[C + 1];
-#pragma unroll
-        for (int c = 0; c < C; ++c) v[c] = pass ? f[c] : 0.0f;
-        v[C] = pass ? 1.0f : 0.0f;
-        if (run_sums<C + 1>(pass ? pix : kEmptySlot, kEmptySlot, v)) {
-            float s[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) s[c] = v[c];
-            table_add<C>(t, sums, counts, pix, s, (int32_t)v[C]);
-        }
-        return;
-    }
-#endif
-#pragma unroll 1
-    for (int it = 0; it < kMaxGroups && rem != 0; ++it) {
-        int leader = __builtin_ctzll(rem);
-        uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pix, leader);
-        uint64_t mm = ballot(pass && pix == p0);
-        int k = __builtin_popcountll(mm);
-        if (k < kMinGroup) break;
-        bool mine = (mm >> lane) & 1;
-        float s[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) s[c] = mine ? f[c] : 0.0f;
-        wave_sum_n<C>(s);
-#if ADOP_ACC_WCACHE
-        wcache_add<C>(w, p0, s, k, t, sums, counts);
-#else
-        if (lane == leader) table_add<C>(t, sums, counts, p0, s, k);
-#endif
-        rem &= ~mm;
-    }
-    if ((rem >> lane) & 1) table_add<C>(t, sums, counts, pix, f, 1);
-}
-
-template <int C>
-__device__ __forceinline__ void acc_table_clear(AccTable<C>& t) {
-    for (int j = threadIdx.x; j < AccTable<C>::H; j += blockDim.x) {
-        t.key[j] = kEmptySlot;
-#pragma unroll
-        for (int c = 0; c < C; ++c) t.sum[c][j] = 0.f;
-        t.cnt[j] = 0;
-    }
-}
-
-// Adds every occupied slot to the global sums and counts and empties it.
-template <int C>
-__device__ __forceinline__ void acc_table_flush(AccTable<C>& t, float* __restrict__ sums, int32_t* __restrict__ counts) {
-    for (int j = threadIdx.x; j < AccTable<C>::H; j += blockDim.x) {
-        uint32_t k = t.key[j];
-        if (k != kEmptySlot) {
-            float* dst = sums + (uint64_t)k * C;
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                atomic_add_f32(dst + c, t.sum[c][j]);
-                t.sum[c][j] = 0.f;
-            }
-            atomic_add_i32(counts + k, t.cnt[j]);
-            t.cnt[j] = 0;
-            t.key[j] = kEmptySlot;
-        }
-    }
-}
-
-template <int C>
-#if ADOP_ACC_WCACHE
-#define ADOP_WC_PARAM , WaveCache<C>& w
-#define ADOP_WC_ARG , w
-#else
-#define ADOP_WC_PARAM
-#define ADOP_WC_ARG
-#endif
-__device__ __forceinline__ void accum_point(const Cam& c, int L, float fa, bool live, float x, float y, float z,
-                                            const float (&f)[C], const uint32_t* __restrict__ keys32, AccTable<C>& t,
-                                            float* __restrict__ sums, int32_t* __restrict__ counts ADOP_WC_PARAM) {
-    Proj p = project(c, x, y, z);
-    bool ok = live && p.ok;
-    // all layers' front depths are gathered before any update, so the
-    // gathers are in flight together
-    uint32_t pix[kMaxLayers];
-    bool in[kMaxLayers];
-    float mz[kMaxLayers];
-#pragma unroll
-    for (int l = 0; l < kMaxLayers; ++l) {
-        pix[l] = 0;
-        in[l] = false;
-        mz[l] = 0.f;
-        if (l < L) {
-            int px = 0, py = 0;
-            in[l] = layer_pixel(c, ok, l, p.u0, p.v0, px, py, pix[l]);
-            mz[l] = __uint_as_float(keys32[2 * (uint64_t)pix[l] + 1]);   // pix is valid for every lane
-        }
-    }
-#pragma unroll
-    for (int l = 0; l < kMaxLayers; ++l) {
-        if (l >= L) break;
-        bool pass = in[l] && p.Z <= __fmul_rn(mz[l], fa);
-        accum_update<C>(pass, pix[l], f, t, sums, counts ADOP_WC_ARG);
-    }
-}
-
-// One view per workgroup: with V views the grid holds V workgroups per
-// point range (view = block % V), so every workgroup's table and wave cache
-// see one view's pixels; the V workgroups of a range are dispatched together
-// and read its points while they are in the caches.  The workgroup table is
-// written out every kAccWindow chunks, before it fills.
-template <int C, typename S>
-__global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_ACCUM_WPE) k_accum(const float* __restrict__ xs, const float* __restrict__ ys,
-                                               const float* __restrict__ zs, const void* __restrict__ feat,
-                                               int64_t n, const ViewRec* __restrict__ views, int V, int L,
-                                               float fa, const uint32_t* __restrict__ keys32,
-                                               float* __restrict__ sums, int32_t* __restrict__ counts) {
-    __shared__ AccTable<C> t;
-    acc_table_clear<C>(t);
-    __syncthreads();
-#if ADOP_ACC_WCACHE
-    WaveCache<C> w;
-    wcache_init<C>(w);
-#endif
-    const int view = V > 1 ? (int)(blockIdx.x % (unsigned)V) : 0;
-    const Cam c0 = load_cam(views + view);
-    RangeMap m = V > 1 ? range_map_views(n, kBlock, V) : range_map(n, kBlock);
-    int since = 0;
-    // the next chunk's points are loaded while the current one is processed
-    float nx = 0.f, ny = 0.f, nz = 0.f, nf[C];
-#pragma unroll
-    for (int ch = 0; ch < C; ++ch) nf[ch] = 0.f;
-    bool nlive = false;
-    auto fetch = [&](int64_t c) {
-        int64_t i = c * kBlock + threadIdx.x;
-        nlive = i < n;
-        if (nlive) {
-            nx = ld_nt(xs + i);
-            ny = ld_nt(ys + i);
-            nz = ld_nt(zs + i);
-            load_feat<C, S>(feat, i, nf);
-        }
-    };
-    if (m.c0 < m.c1) fetch(m.c0);
-    for (int64_t c = m.c0; c < m.c1; ++c) {
-        const bool live = nlive;
-        const float x = nx, y = ny, z = nz;
-        float f[C];
-#pragma unroll
-        for (int ch = 0; ch < C; ++ch) f[ch] = nf[ch];
-        if (c + 1 < m.c1) fetch(c + 1);
-        accum_point<C>(c0, L, fa, live, x, y, z, f, keys32, t, sums, counts ADOP_WC_ARG);
-        if (kAccWindow > 0 && ++since == kAccWindow) {   // uniform in the workgroup
-            since = 0;
-            __syncthreads();
-            acc_table_flush<C>(t, sums, counts);
-            __syncthreads();
-        }
-    }
-#if ADOP_ACC_WCACHE
-    wcache_flush<C>(w, t, sums, counts);
-#endif
-    __syncthreads();
-    acc_table_flush<C>(t, sums, counts);
-}
-
-struct Background {
-    float v[16];
-};
-
-template <int C>
-__global__ void __launch_bounds__(256) k_normalize(const ViewRec* __restrict__ views, int L,
-                                                   const float* __restrict__ sums,
-                                                   const int32_t* __restrict__ counts,
-                                                   float* __restrict__ images, Background bg) {
-    int vl = blockIdx.y;
-    int v = vl / L, l = vl - (vl / L) * L;
-    const ViewRec& c = views[v];
-    int64_t npx = (int64_t)c.lw[l] * c.lh[l];
-    uint64_t base = c.base[l];
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < npx; j += (int64_t)gridDim.x * blockDim.x) {
-        uint64_t p = base + (uint64_t)j;
-        int32_t k = counts[p];
-        const float* s = sums + p * C;
-        float* out = images + (uint64_t)C * base + (uint64_t)j;
-#pragma unroll
-        for (int ch = 0; ch < C; ++ch) {
-            float val = k > 0 ? __fdiv_rn(s[ch], (float)k) : bg.v[ch];
-            out[(uint64_t)ch * (uint64_t)npx] = val;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// backward
-// ---------------------------------------------------------------------------
-
-template <int C>
-__global__ void __launch_bounds__(256) k_pack(const ViewRec* __restrict__ views, int L,
-                                              const uint64_t* __restrict__ keys,
-                                              const int32_t* __restrict__ counts,
-                                              const float* __restrict__ images,
-                                              const float* __restrict__ grad,
-                                              float* __restrict__ pack, float fa, Background bg) {
-    using PL = PackLayout<C>;
-    int vl = blockIdx.y;
-    int v = vl / L, l = vl - (vl / L) * L;
-    const ViewRec& c = views[v];
-    int64_t npx = (int64_t)c.lw[l] * c.lh[l];
-    uint64_t base = c.base[l];
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < npx; j += (int64_t)gridDim.x * blockDim.x) {
-        uint64_t p = base + (uint64_t)j;
-        int32_t k = counts[p];
-        uint32_t minz = (uint32_t)(keys[p] >> 32);
-        const float* gi = grad + (uint64_t)C * base + (uint64_t)j;
-        const float* ii = images + (uint64_t)C * base + (uint64_t)j;
-        float rec[PL::stride];
-        float gdot = 0.f;
-#pragma unroll
-        for (int ch = 0; ch < C; ++ch) {
-            float g = gi[(uint64_t)ch * (uint64_t)npx];
-            float I = k > 0 ? ii[(uint64_t)ch * (uint64_t)npx] : bg.v[ch];
-            rec[ch] = g;
-            gdot = __fmaf_rn(g, I, gdot);
-        }
-        const float inf = __builtin_inff();
-        const float mzf = __uint_as_float(minz);
-        rec[PL::gdot] = gdot;
-        rec[PL::minz] = k > 0 ? mzf : inf;
-        rec[PL::behind] = k > 0 ? __fmul_rn(mzf, fa) : inf;
-        rec[PL::count] = (float)k;
-#pragma unroll
-        for (int q = PL::used; q < PL::stride; ++q) rec[q] = 0.f;
-        float4* dst = reinterpret_cast<float4*>(pack + p * PL::stride);
-#pragma unroll
-        for (int q = 0; q < PL::stride / 4; ++q)
-            dst[q] = make_float4(rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], rec[4 * q + 3]);
-    }
-}
-
-// <G(q), dI> for the point virtually moved into neighbour q (Eq. spatialderiv):
-// empty q -> tau - b; point hidden behind q (z > (1+alpha) min_z(q)) -> 0;
-// point in front (z (1+alpha) < min_z(q)) -> tau - I(q); otherwise the point
-// joins q's blend set -> (tau - I(q)) / (n+1).  With gdot = <G, I(q)> (or
-// <G, b>), every case is factor * (<G(q), tau> - gdot).
-template <int C>
-__device__ __forceinline__ void load_rec(const float* __restrict__ pack, uint64_t q,
-                                         float (&rec)[PackLayout<C>::stride]) {
-    using PL = PackLayout<C>;
-    const float4* r4 = reinterpret_cast<const float4*>(pack + q * PL::stride);
-#pragma unroll
-    for (int k = 0; k < PL::stride / 4; ++k) {
-        float4 t4 = r4[k];
-        rec[4 * k] = t4.x;
-        rec[4 * k + 1] = t4.y;
-        rec[4 * k + 2] = t4.z;
-        rec[4 * k + 3] = t4.w;
-    }
-}
-
-template <int C>
-__device__ __forceinline__ float induced_rec(const float (&rec)[PackLayout<C>::stride], float Z, float Zfa,
-                                             const float (&tau)[C]) {
-    using PL = PackLayout<C>;
-    float dot = 0.f;
-#pragma unroll
-    for (int ch = 0; ch < C; ++ch) dot = __fmaf_rn(rec[ch], tau[ch], dot);
-    float t = dot - rec[PL::gdot];
-    float factor = __builtin_amdgcn_rcpf(rec[PL::count] + 1.0f);
-    factor = (Zfa < rec[PL::minz]) ? 1.0f : factor;        // in front, or q empty
-    factor = (Z > rec[PL::behind]) ? 0.0f : factor;        // hidden behind q
-    return factor * t;
-}
-
-// A layer where the point is in its pixel's blend set (or every in-bounds
-// point with SPATIAL_ALL): the own record and the four neighbour records are
-// loaded together, then dtau += G/n (if vis) and dL/du, dL/dv.
-template <int C>
-__device__ __forceinline__ void layer_work(const float* __restrict__ pack, uint32_t pix, int qx, int qy, int lw,
-                                           int lh, float Z, float fa, bool vis, const float (&tau)[C],
-                                           float (&dt)[C], float& du, float& dv) {
-    using PL = PackLayout<C>;
-    float own[PL::stride], rr[PL::stride], rl[PL::stride], rd[PL::stride], ru[PL::stride];
-    const bool hr = qx + 1 < lw, hl = qx > 0, hd = qy + 1 < lh, hu = qy > 0;
-    load_rec<C>(pack, pix, own);
-    load_rec<C>(pack, hr ? (uint64_t)pix + 1 : (uint64_t)pix, rr);
-    load_rec<C>(pack, hl ? (uint64_t)pix - 1 : (uint64_t)pix, rl);
-    load_rec<C>(pack, hd ? (uint64_t)pix + lw : (uint64_t)pix, rd);
-    load_rec<C>(pack, hu ? (uint64_t)pix - lw : (uint64_t)pix, ru);
-    if (vis) {
-        float inv = __builtin_amdgcn_rcpf(own[PL::count]);
-#pragma unroll
-        for (int ch = 0; ch < C; ++ch) dt[ch] = __fmaf_rn(own[ch], inv, dt[ch]);
-    }
-    const float Zfa = __fmul_rn(Z, fa);
-    float tr = hr ? induced_rec<C>(rr, Z, Zfa, tau) : 0.f;
-    float tl = hl ? induced_rec<C>(rl, Z, Zfa, tau) : 0.f;
-    float td = hd ? induced_rec<C>(rd, Z, Zfa, tau) : 0.f;
-    float tu = hu ? induced_rec<C>(ru, Z, Zfa, tau) : 0.f;
-    du = tr - tl;
-    dv = td - tu;
-}
-
-// One point in one view: dL/du0, dL/dv0 summed over layers, then the chain
-// through the projection; adds the 15 pose/intrinsics terms to acc (FP32).
-// The layer loop is not unrolled (it keeps the kernel within the instruction
-// cache); w_l = w >> l, h_l = h >> l and layer bases follow one another.
-template <int C>
-__device__ __forceinline__ void point_view(const Cam& c, int L, float fa, bool spatial_all,
-                                           const float* __restrict__ pack, bool live, float x, float y, float z,
-                                           const float (&tau)[C], float (&dt)[C], float (&dp)[3], float (&acc)[15],
-                                           bool& any) {
-    using PL = PackLayout<C>;
-    Proj p = project(c, x, y, z);
-    if (!(live && p.ok)) return;
-    float gu = 0.f, gv = 0.f;
-#if ADOP_BWD_HOIST
-    // bit l of work: the layer needs the neighbour records; bit l of seen:
-    // the point is in the layer's blend set
-    uint32_t work = 0, seen = 0;
-    {
-        float mz[kMaxLayers];
-        bool in[kMaxLayers];
-#pragma unroll
-        for (int l = 0; l < kMaxLayers; ++l) {
-            mz[l] = 0.f;
-            in[l] = false;
-            if (l < L) {
-                int qx = 0, qy = 0;
-                uint32_t pix = 0;
-                in[l] = layer_pixel(c, true, l, p.u0, p.v0, qx, qy, pix);
-                mz[l] = pack[(uint64_t)pix * PL::stride + PL::behind];   // pix is valid for every lane
-            }
-        }
-#pragma unroll
-        for (int l = 0; l < kMaxLayers; ++l) {
-            const bool vis = in[l] && p.Z <= mz[l];   // Eq. depthtest against (1+alpha) min_z
-            seen |= (uint32_t)vis << l;
-            work |= (uint32_t)(vis || (spatial_all && in[l])) << l;
-        }
-    }
-    uint32_t base = c.base[0];
-#pragma unroll 1
-    for (int l = 0; l < L; ++l) {
-        const int lw = c.w >> l, lh = c.h >> l;
-        const uint32_t lbase = base;
-        base += (uint32_t)lw * (uint32_t)lh;
-        if (!((work >> l) & 1u)) continue;
-        int qx = 0, qy = 0;
-        uint32_t pix = 0;
-        layer_pixel_at(true, l, lw, lh, lbase, p.u0, p.v0, qx, qy, pix);
-        const bool vis = (seen >> l) & 1u;
-#else
-    uint32_t base = c.base[0];
-#pragma unroll 1
-    for (int l = 0; l < L; ++l) {
-        const int lw = c.w >> l, lh = c.h >> l;
-        int qx = 0, qy = 0;
-        uint32_t pix = 0;
-        const bool in = layer_pixel_at(true, l, lw, lh, base, p.u0, p.v0, qx, qy, pix);
-        base += (uint32_t)lw * (uint32_t)lh;
-        const float mz = pack[(uint64_t)pix * PL::stride + PL::behind];   // pix is valid for every lane
-        const bool vis = in && p.Z <= mz;
-        if (!(vis || (spatial_all && in))) continue;
-#endif
-        float du = 0.f, dv = 0.f;
-        layer_work<C>(pack, pix, qx, qy, lw, lh, p.Z, fa, vis, tau, dt, du, dv);
-        const float s = 0.5f * layer_scale(l);
-        gu = __fmaf_rn(du, s, gu);
-        gv = __fmaf_rn(dv, s, gv);
-    }
-    if (gu == 0.f && gv == 0.f) return;
-    any = true;
-    const float a = p.a, b = p.b, r2 = p.r2, D = p.D;
-    const float Dp = __fmaf_rn(r2, __fmaf_rn(r2, 3.0f * c.k3, 2.0f * c.k2), c.k1);
-    const float xa = D + 2.0f * a * a * Dp + 2.0f * c.p1 * b + 6.0f * c.p2 * a;
-    const float xb = 2.0f * a * b * Dp + 2.0f * c.p1 * a + 2.0f * c.p2 * b;
-    const float yb = D + 2.0f * b * b * Dp + 6.0f * c.p1 * b + 2.0f * c.p2 * a;
-    const float gux = gu * c.fx, gvy = gv * c.fy;
-    const float ga = gux * xa + gvy * xb;
-    const float gb = gux * xb + gvy * yb;
-    const float iz = __builtin_amdgcn_rcpf(p.Z);
-    const float gcx = ga * iz, gcy = gb * iz, gcz = -(a * ga + b * gb) * iz;
-    dp[0] += c.R[0] * gcx + c.R[3] * gcy + c.R[6] * gcz;
-    dp[1] += c.R[1] * gcx + c.R[4] * gcy + c.R[7] * gcz;
-    dp[2] += c.R[2] * gcx + c.R[5] * gcy + c.R[8] * gcz;
-    const float au = gux * a + gvy * b;
-    const float r4 = r2 * r2;
-    acc[0] += gcx;
-    acc[1] += gcy;
-    acc[2] += gcz;
-    acc[3] += p.Y * gcz - p.Z * gcy;
-    acc[4] += p.Z * gcx - p.X * gcz;
-    acc[5] += p.X * gcy - p.Y * gcx;
-    acc[6] += gu * p.xd;
-    acc[7] += gv * p.yd;
-    acc[8] += gu;
-    acc[9] += gv;
-    acc[10] += au * r2;
-    acc[11] += au * r4;
-    acc[12] += au * r4 * r2;
-    acc[13] += gux * 2.0f * a * b + gvy * (r2 + 2.0f * b * b);
-    acc[14] += gux * (r2 + 2.0f * a * a) + gvy * 2.0f * a * b;
-}
-
-// The 15 terms of the PPL points of a lane (FP32, at most PPL terms each) are
-// widened to FP64 and summed over the wave in a fixed DPP order; each wave
-// owns its LDS slot, so the sum order is fixed for a fixed grid.
-__device__ __forceinline__ void reduce_terms(const float (&acc)[15], bool any, double* __restrict__ slot, int lane) {
-    if (ballot(any) == 0) return;
-#pragma unroll
-    for (int t = 0; t < 15; ++t) {
-        double s = wave_sum_f64((double)acc[t]);
-        if (lane == 0) slot[t] += s;
-    }
-}
-
-constexpr int kSuper = 4;   // chunks a lane sums in FP32 before widening (single view)
-
-template <int C, typename S, int PPL, bool SINGLE>
-__global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_BWD_WPE) k_backward(const float* __restrict__ xs, const float* __restrict__ ys,
-                                                  const float* __restrict__ zs, const void* __restrict__ feat,
-                                                  int64_t n, const ViewRec* __restrict__ views, int V, int L,
-                                                  float fa, uint32_t flags, const float* __restrict__ pack,
-                                                  float* __restrict__ dfeat, float* __restrict__ dpos,
-                                                  double* __restrict__ partials) {
-    // single view: [256 lanes][16] FP64 per-lane sums; several views:
-    // [4 waves][V][16] per-wave sums
-    extern __shared__ double acc_lds[];
-    const int wave = threadIdx.x / kWave;
-    const int lane = threadIdx.x % kWave;
-    const int slots = SINGLE ? kBlock * 16 : 4 * V * 16;
-    for (int j = threadIdx.x; j < slots; j += blockDim.x) acc_lds[j] = 0.0;
-    __syncthreads();
-    const bool spatial_all = (flags & 1u) != 0;
-    const Cam c0 = load_cam(views);
-    float acc1[15];
-#pragma unroll
-    for (int t = 0; t < 15; ++t) acc1[t] = 0.f;
-    int since = 0;
-
-    RangeMap m = range_map(n, (int64_t)kBlock * PPL);
-    for (int64_t c = m.c0; c < m.c1; ++c) {
-        const int64_t wbase = c * kBlock * PPL + (int64_t)wave * kWave * PPL;
-        float px_[PPL], py_[PPL], pz_[PPL];
-        float tau[PPL][C], dt[PPL][C], dp[PPL][3];
-        bool live[PPL];
-#pragma unroll
-        for (int k = 0; k < PPL; ++k) {
-            int64_t i = wbase + (int64_t)k * kWave + lane;
-            live[k] = i < n;
-            px_[k] = py_[k] = pz_[k] = 0.f;
-#pragma unroll
-            for (int ch = 0; ch < C; ++ch) { tau[k][ch] = 0.f; dt[k][ch] = 0.f; }
-            dp[k][0] = dp[k][1] = dp[k][2] = 0.f;
-            if (live[k]) {
-                px_[k] = ld_nt(xs + i);
-                py_[k] = ld_nt(ys + i);
-                pz_[k] = ld_nt(zs + i);
-                load_feat<C, S>(feat, i, tau[k]);
-            }
-        }
-        if (SINGLE) {
-            bool any = false;
-#pragma unroll
-            for (int k = 0; k < PPL; ++k)
-                point_view<C>(c0, L, fa, spatial_all, pack, live[k], px_[k], py_[k], pz_[k], tau[k], dt[k], dp[k],
-                              acc1, any);
-            if (++since == kSuper || c + 1 == m.c1) {
-                double* slot = acc_lds + threadIdx.x * 16;
-#pragma unroll
-                for (int t = 0; t < 15; ++t) {
-                    slot[t] += (double)acc1[t];
-                    acc1[t] = 0.f;
-                }
-                since = 0;
-            }
-        } else {
-            for (int v = 0; v < V; ++v) {
-                const Cam cv = load_cam(views + v);
-                float acc[15];
-#pragma unroll
-                for (int t = 0; t < 15; ++t) acc[t] = 0.f;
-                bool any = false;
-#pragma unroll
-                for (int k = 0; k < PPL; ++k)
-                    point_view<C>(cv, L, fa, spatial_all, pack, live[k], px_[k], py_[k], pz_[k], tau[k], dt[k],
-                                  dp[k], acc, any);
-                reduce_terms(acc, any, acc_lds + (wave * V + v) * 16, lane);
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < PPL; ++k) {
-            if (!live[k]) continue;
-            int64_t i = wbase + (int64_t)k * kWave + lane;
-            store_f32_row<C>(dfeat, i, dt[k]);
-            st_nt(dpos + i, dp[k][0]);
-            st_nt(dpos + n + i, dp[k][1]);
-            st_nt(dpos + 2 * n + i, dp[k][2]);
-        }
-    }
-    __syncthreads();
-    if (SINGLE) {
-        // fixed-order sum of the 256 lanes' FP64 partials: 16 threads per
-        // term each sum 16 lanes, then one thread sums the 16 results
-        __shared__ double red[16][16];
-        const int t = threadIdx.x & 15, part = threadIdx.x >> 4;
-        double s = 0.0;
-        for (int j = 0; j < 16; ++j) s += acc_lds[(part * 16 + j) * 16 + t];
-        red[part][t] = s;
-        __syncthreads();
-        if (threadIdx.x < 16) {
-            double r = 0.0;
-            for (int j = 0; j < 16; ++j) r += red[j][threadIdx.x];
-            partials[(uint64_t)blockIdx.x * 16 + threadIdx.x] = r;
-        }
-    } else {
-        for (int j = threadIdx.x; j < V * 16; j += blockDim.x) {
-            double s = 0.0;
-            for (int w = 0; w < 4; ++w) s += acc_lds[w * V * 16 + j];
-            partials[(uint64_t)blockIdx.x * V * 16 + j] = s;
-        }
-    }
-}
-
-// Fixed-order FP64 sum over workgroup partials; block v writes view v.
-__global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ partials, int groups, int V,
-                                                double* __restrict__ dpose, double* __restrict__ dintr) {
-    __shared__ double red[256][16];
-    int v = blockIdx.x;
-    double s[16];
-#pragma unroll
-    for (int t = 0; t < 16; ++t) s[t] = 0.0;
-    for (int g = threadIdx.x; g < groups; g += blockDim.x) {
-        const double* p = partials + ((uint64_t)g * V + v) * 16;
-#pragma unroll
-        for (int t = 0; t < 16; ++t) s[t] += p[t];
-    }
-#pragma unroll
-    for (int t = 0; t < 16; ++t) red[threadIdx.x][t] = s[t];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-#pragma unroll
-            for (int t = 0; t < 16; ++t) red[threadIdx.x][t] += red[threadIdx.x + w][t];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x < 6) dpose[v * 6 + threadIdx.x] = red[0][threadIdx.x];
-    else if (threadIdx.x < 15) dintr[v * 9 + threadIdx.x - 6] = red[0][threadIdx.x];
-}
-
-// ---------------------------------------------------------------------------
-// launchers
-// ---------------------------------------------------------------------------
-
-static inline Background make_bg(const float* bg, int C) {
-    Background b;
-    for (int c = 0; c < 16; ++c) b.v[c] = (bg && c < C) ? bg[c] : 0.0f;
-    return b;
-}
-
-static inline unsigned grid_for(int64_t items, int64_t per_group, int cap) {
-    int64_t g = (items + per_group - 1) / per_group;
-    g = (g + kXcds - 1) / kXcds * kXcds;
-    if (g < kXcds) g = kXcds;
-    if (g > cap) g = cap;
-    return (unsigned)g;
-}
-
-// Resident workgroups per CU of a kernel (persistent grids).
-template <typename K>
-static int resident(K kernel, size_t dyn_lds) {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, dyn_lds) != hipSuccess || nb < 1) nb = 1;
-    return nb;
-}
-
-// Persistent grid: every CU full once, a multiple of 8 (one range per
-// workgroup, XCD-major), and no more workgroups than chunks.
-static inline unsigned persistent_grid(int64_t n, int64_t chunk, int cus, int per_cu, int cap) {
-    int64_t g = (int64_t)cus * per_cu;
-    g = g / kXcds * kXcds;
-    int64_t need = (n + chunk - 1) / chunk;
-    need = (need + kXcds - 1) / kXcds * kXcds;
-    g = std::min<int64_t>(g, need);
-    g = std::min<int64_t>(g, cap);
-    if (g < kXcds) g = kXcds;
-    return (unsigned)g;
-}
-
-template <int C, typename S, bool SINGLE>
-static void forward_points(const FwdArgs& a, hipStream_t st) {
-    static const int occ_depth = resident(k_depth<SINGLE>, 0);
-    static const int occ_accum = resident(k_accum<C, S>, 0);
-    unsigned gd = persistent_grid(a.n, kBlock, a.cus, occ_depth, 1 << 20);
-    a.timer.mark(kKDepth, 0, st);
-    k_depth<SINGLE><<<gd, kBlock, 0, st>>>(a.x, a.y, a.z, a.orig, a.n, a.views, a.V, a.L, a.keys);
-    a.timer.mark(kKDepth, 1, st);
-    unsigned ga = persistent_grid(a.n, kBlock, a.cus, occ_accum, 1 << 20);
-    if (!SINGLE) {
-        // V workgroups (one per view) per point range
-        int64_t ranges = std::max<int64_t>(kXcds, (int64_t)ga / a.V / kXcds * kXcds);
-        ranges = std::min<int64_t>(ranges, (a.n + kBlock - 1) / kBlock);
-        ga = (unsigned)(std::max<int64_t>(ranges, 1) * a.V);
-    }
-    a.timer.mark(kKAccum, 0, st);
-    k_accum<C, S><<<ga, kBlock, 0, st>>>(a.x, a.y, a.z, a.feat, a.n, a.views, a.V, a.L, a.fa,
-                                                  reinterpret_cast<const uint32_t*>(a.keys), a.sums, a.counts);
-    a.timer.mark(kKAccum, 1, st);
-}
-
-template <int C, typename S>
-static hipError_t forward_impl(const FwdArgs& a, hipStream_t st) {
+void launch_clear(const FwdArgs& a, int64_t nsums, hipStream_t st) {
     unsigned gp = grid_for(a.pixels, 256 * 4, a.cus * 8);
     a.timer.mark(kKClear, 0, st);
-    k_clear<<<gp, 256, 0, st>>>(a.keys, a.counts, a.sums, a.pixels, a.pixels * C);
+    k_clear<<<gp, 256, 0, st>>>(a.keys, a.counts, a.sums, a.pixels, nsums);
     a.timer.mark(kKClear, 1, st);
-    if (a.n > 0) {
-        if (a.V == 1) forward_points<C, S, true>(a, st);
-        else forward_points<C, S, false>(a, st);
-    }
-    dim3 gn((unsigned)std::min<int64_t>((a.max_layer_pixels + 255) / 256, 1024), (unsigned)(a.V * a.L));
-    a.timer.mark(kKNormalize, 0, st);
-    k_normalize<C><<<gn, 256, 0, st>>>(a.views, a.L, a.sums, a.counts, a.images, make_bg(a.background, C));
-    a.timer.mark(kKNormalize, 1, st);
-    return hipGetLastError();
 }
 
-template <int C, typename S, bool SINGLE>
-static unsigned backward_points(const BwdArgs& a, hipStream_t st) {
-    constexpr int PPL = C <= 4 ? ADOP_PPL4 : 2;
-    const size_t lds = SINGLE ? (size_t)kBlock * 16 * sizeof(double) : (size_t)4 * a.V * 16 * sizeof(double);
-    static const int occ = resident(k_backward<C, S, PPL, SINGLE>,
-                                    SINGLE ? lds : (size_t)4 * kMaxViewsBwd * 16 * sizeof(double));
-    unsigned g = persistent_grid(a.n, (int64_t)kBlock * PPL, a.cus, occ, a.groups);
-    a.timer.mark(kKBackward, 0, st);
-    k_backward<C, S, PPL, SINGLE><<<g, kBlock, lds, st>>>(a.x, a.y, a.z, a.feat, a.n, a.views, a.V, a.L, a.fa,
-                                                          a.flags, a.pack, a.dfeat, a.dpos, a.partials);
-    a.timer.mark(kKBackward, 1, st);
-    return g;
+template <bool SINGLE, bool OPTS>
+static void depth_pass(const FwdArgs& a, hipStream_t st) {
+    static const int occ = resident(k_depth<SINGLE, OPTS>, 0);
+    const unsigned gd = persistent_grid(a.n, kBlock, a.cus, occ, 1 << 20);
+    k_depth<SINGLE, OPTS><<<gd, kBlock, 0, st>>>(a.x, a.y, a.z, a.orig, a.n, a.views, a.V, a.L, a.opts, a.keys);
 }
 
-template <int C, typename S>
-static hipError_t backward_impl(const BwdArgs& a, hipStream_t st) {
-    dim3 gn((unsigned)std::min<int64_t>((a.max_layer_pixels + 255) / 256, 1024), (unsigned)(a.V * a.L));
-    a.timer.mark(kKPack, 0, st);
-    k_pack<C><<<gn, 256, 0, st>>>(a.views, a.L, a.keys, a.counts, a.images, a.grad, a.pack, a.fa,
-                                 make_bg(a.background, C));
-    a.timer.mark(kKPack, 1, st);
-    unsigned g = a.V == 1 ? backward_points<C, S, true>(a, st) : backward_points<C, S, false>(a, st);
+void launch_depth(const FwdArgs& a, hipStream_t st) {
+    const bool opts = a.opts.flags & (kOptCullBack | kOptCullPrinted | kOptDiscard);
+    a.timer.mark(kKDepth, 0, st);
+    if (a.V == 1) opts ? depth_pass<true, true>(a, st) : depth_pass<true, false>(a, st);
+    else opts ? depth_pass<false, true>(a, st) : depth_pass<false, false>(a, st);
+    a.timer.mark(kKDepth, 1, st);
+}
+
+void launch_reduce(const BwdArgs& a, unsigned groups, hipStream_t st) {
     a.timer.mark(kKReduce, 0, st);
-    k_reduce<<<a.V, 256, 0, st>>>(a.partials, (int)g, a.V, a.dpose, a.dintr);
+    k_reduce<<<a.V, 256, 0, st>>>(a.partials, (int)groups, a.V, a.dpose, a.dintr);
     a.timer.mark(kKReduce, 1, st);
-    return hipGetLastError();
 }
 
 int backward_points_per_group(int C) { return kBlock * (C <= 4 ? ADOP_PPL4 : 2); }
 
-#define ADOP_DISPATCH_C(FN, S, ARGS, ST)            \
-    switch (ARGS.C) {                               \
-        case 1: return FN<1, S>(ARGS, ST);          \
-        case 2: return FN<2, S>(ARGS, ST);          \
-        case 3: return FN<3, S>(ARGS, ST);          \
-        case 4: return FN<4, S>(ARGS, ST);          \
-        case 5: return FN<5, S>(ARGS, ST);          \
-        case 6: return FN<6, S>(ARGS, ST);          \
-        case 7: return FN<7, S>(ARGS, ST);          \
-        case 8: return FN<8, S>(ARGS, ST);          \
-        case 9: return FN<9, S>(ARGS, ST);          \
-        case 10: return FN<10, S>(ARGS, ST);        \
-        case 11: return FN<11, S>(ARGS, ST);        \
-        case 12: return FN<12, S>(ARGS, ST);        \
-        case 13: return FN<13, S>(ARGS, ST);        \
-        case 14: return FN<14, S>(ARGS, ST);        \
-        case 15: return FN<15, S>(ARGS, ST);        \
-        case 16: return FN<16, S>(ARGS, ST);        \
-        default: return hipErrorInvalidValue;       \
-    }
-
-#ifdef ADOP_TUNE_C4_F32_ONLY
-// tuning builds: only 4 channels FP32 and 8 channels BF16
 hipError_t launch_forward(const FwdArgs& a, hipStream_t st) {
-    if (a.C == 4 && a.dtype == 0) return forward_impl<4, F32>(a, st);
-    if (a.C == 8 && a.dtype == 1) return forward_impl<8, BF16>(a, st);
-    return hipErrorInvalidValue;
-}
-hipError_t launch_backward(const BwdArgs& a, hipStream_t st) {
-    if (a.C == 4 && a.dtype == 0) return backward_impl<4, F32>(a, st);
-    if (a.C == 8 && a.dtype == 1) return backward_impl<8, BF16>(a, st);
-    return hipErrorInvalidValue;
-}
-#else
-hipError_t launch_forward(const FwdArgs& a, hipStream_t st) {
-    switch (a.dtype) {
-        case 0: ADOP_DISPATCH_C(forward_impl, F32, a, st)
-        case 1: ADOP_DISPATCH_C(forward_impl, BF16, a, st)
-        case 2: ADOP_DISPATCH_C(forward_impl, F16, a, st)
-        default: return hipErrorInvalidValue;
+    if (a.C < 1 || a.C > 16) return hipErrorInvalidValue;
+    switch ((a.C - 1) / 4) {
+        case 0: return forward_group_1(a, st);
+        case 1: return forward_group_2(a, st);
+        case 2: return forward_group_3(a, st);
+        default: return forward_group_4(a, st);
     }
 }
 
 hipError_t launch_backward(const BwdArgs& a, hipStream_t st) {
-    switch (a.dtype) {
-        case 0: ADOP_DISPATCH_C(backward_impl, F32, a, st)
-        case 1: ADOP_DISPATCH_C(backward_impl, BF16, a, st)
-        case 2: ADOP_DISPATCH_C(backward_impl, F16, a, st)
-        default: return hipErrorInvalidValue;
+    if (a.C < 1 || a.C > 16) return hipErrorInvalidValue;
+    switch ((a.C - 1) / 4) {
+        case 0: return backward_group_1(a, st);
+        case 1: return backward_group_2(a, st);
+        case 2: return backward_group_3(a, st);
+        default: return backward_group_4(a, st);
     }
 }
-#endif
 
 }  // namespace adop

@@ -154,7 +154,22 @@ struct DevBuf {
     ~DevBuf() { if (p) (void)hipFree(p); }
 };
 
+__global__ void __launch_bounds__(256) k_scene_gather(const float* __restrict__ src, int comp, int64_t n,
+                                                      const int32_t* __restrict__ orig, float* __restrict__ dst) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = orig[i];
+        for (int k = 0; k < comp; ++k) dst[(int64_t)k * n + i] = src[o * comp + k];
+    }
+}
+
 }  // namespace
+
+hipError_t scene_gather(const float* src, int comp, int64_t n, const int32_t* orig, float* dst, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+    k_scene_gather<<<g, 256, 0, st>>>(src, comp, n, orig, dst);
+    return hipGetLastError();
+}
 
 hipError_t scene_prepare(const PrepArgs& a, hipStream_t st) {
     const int64_t n = a.n;

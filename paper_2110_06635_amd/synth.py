@@ -183,9 +183,10 @@ def uniform_box(n: int, half: float, c: int, seed: int):
 
 
 def planes(n_planes: int, per_plane: int, c: int, seed: int, box: float = 5.0,
-           half_lo: float = 0.5, half_hi: float = 2.0, sigma: float = 0.01):
+           half_lo: float = 0.5, half_hi: float = 2.0, sigma: float = 0.01, with_normals: bool = False):
     """Points on seeded random squares: centre U[-box,box]^3, random unit
-    normal, half-extent U[half_lo,half_hi], in-plane U, normal offset N(0,sigma^2)."""
+    normal, half-extent U[half_lo,half_hi], in-plane U, normal offset N(0,sigma^2).
+    with_normals: also return each point's plane normal [n,3] float32."""
     rg, rp, rf = _streams(seed, 3)
     centres = rg.uniform(-box, box, size=(n_planes, 3))
     normals = rg.normal(size=(n_planes, 3))
@@ -206,7 +207,30 @@ def planes(n_planes: int, per_plane: int, c: int, seed: int, box: float = 5.0,
     for s in range(0, n, CHUNK):
         m = min(CHUNK, n - s)
         feat[s:s + m] = rf.random((m, c))
+    if with_normals:
+        return pos, feat, np.repeat(normals, per_plane, axis=0).astype(np.float32)
     return pos, feat
+
+
+def unit_vectors(n: int, seed: int) -> np.ndarray:
+    """Seeded random unit vectors [n,3] float32 (per-point normals)."""
+    (r,) = _streams(seed, 1)
+    v = np.empty((n, 3), np.float32)
+    for s in range(0, n, CHUNK):
+        m = min(CHUNK, n - s)
+        w = r.normal(size=(m, 3))
+        v[s:s + m] = w / np.linalg.norm(w, axis=1, keepdims=True)
+    return v
+
+
+def uniform01(n: int, seed: int) -> np.ndarray:
+    """Seeded U[0,1) float32 [n] (the per-point beta of stochastic discarding)."""
+    (r,) = _streams(seed, 1)
+    out = np.empty(n, np.float32)
+    for s in range(0, n, CHUNK):
+        m = min(CHUNK, n - s)
+        out[s:s + m] = r.random(m, dtype=np.float32)
+    return out
 
 
 def gaussian_mixture(n: int, k: int, box: float, sigma: float, c: int, seed: int):

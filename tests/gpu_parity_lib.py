@@ -87,21 +87,31 @@ def compare_backward(scene, got, ref, tol_feat=1e-5, tol_pos=1e-4, tol_cam=1e-5)
     return report
 
 
-def run_case(A, ctx, O, s, dtype="f32", prepare=True, flags=0, grad_seed=99, backward=True, alpha=None):
-    """Forward (+ backward) on GPU and oracle; returns reports."""
+def run_case(A, ctx, O, s, dtype="f32", prepare=True, flags=0, grad_seed=99, backward=True, alpha=None,
+             normals=None, radius=None, beta=None, gamma=1.5):
+    """Forward (+ backward) on GPU and oracle; returns reports.  normals
+    [n,3], radius [n] and beta [n] (caller's order) go with the culling and
+    discarding flags."""
     import torch
     alpha = s.alpha if alpha is None else alpha
     scene, widened = to_device_scene(A, ctx, s, dtype, prepare)
-    fr = gpu_forward(A, ctx, scene, s, alpha=alpha, flags=flags)
-    ref = O.forward(s.pos, widened, s.cams, s.layers, alpha=alpha, background=s.bg(), want64=True)
+    if normals is not None:
+        scene.set_normals(ctx, torch.from_numpy(np.ascontiguousarray(normals, np.float32)).cuda())
+    if beta is not None:
+        scene.set_discard(ctx, torch.from_numpy(np.ascontiguousarray(beta, np.float32)).cuda(),
+                          torch.from_numpy(np.ascontiguousarray(radius, np.float32)).cuda())
+    opt = dict(flags=flags, normals=normals, radius=radius, beta=beta, gamma=gamma)
+    fr = A.render_forward(ctx, scene, s.cams, s.layers, alpha=alpha, flags=flags, background=s.bg(), gamma=gamma)
+    torch.cuda.synchronize()
+    ref = O.forward(s.pos, widened, s.cams, s.layers, alpha=alpha, background=s.bg(), want64=True, **opt)
     scale = max(1.0, float(np.max(np.abs(widened))) if widened.size else 1.0)
     rep = {"image_rel": compare_forward(fr, ref, scale=scale)}
     if backward:
         total = fr.pixels
         G = synth.upstream_grad(total * s.c, grad_seed)
         g = torch.from_numpy(G).cuda()
-        got = A.render_backward(ctx, scene, fr, g, alpha=alpha, flags=flags, background=s.bg())
+        got = A.render_backward(ctx, scene, fr, g, alpha=alpha, flags=flags, background=s.bg(), gamma=gamma)
         torch.cuda.synchronize()
-        rb = O.backward(s.pos, widened, s.cams, s.layers, G, alpha=alpha, background=s.bg(), flags=flags)
+        rb = O.backward(s.pos, widened, s.cams, s.layers, G, alpha=alpha, background=s.bg(), **opt)
         rep.update(compare_backward(scene, got, rb))
     return rep
