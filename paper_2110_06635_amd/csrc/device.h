@@ -156,27 +156,45 @@ __device__ __forceinline__ float sqrt_rn(float x) {
     return y;
 }
 
-// Eq. normalculling for point i (see kOptCull*): the sign of (R n) . x_c in
-// FP32 with the nesting of the projection.
+// Optional per-point inputs of one point (loaded with the point's position,
+// so that their latency hides behind the same wait).
+struct PointExtra {
+    float nx = 0.f, ny = 0.f, nz = 0.f, r = 0.f, beta = 0.f;
+};
+
+__device__ __forceinline__ void load_extra(const PointOpts& o, int64_t i, PointExtra& e) {
+    if (o.flags & (kOptCullBack | kOptCullPrinted)) {
+        e.nx = __builtin_nontemporal_load(o.nx + i);
+        e.ny = __builtin_nontemporal_load(o.ny + i);
+        e.nz = __builtin_nontemporal_load(o.nz + i);
+    }
+    if (o.flags & kOptDiscard) {
+        e.r = __builtin_nontemporal_load(o.radius + i);
+        e.beta = __builtin_nontemporal_load(o.beta + i);
+    }
+}
+
+// Eq. normalculling (see kOptCull*): the sign of (R n) . x_c in FP32 with
+// the nesting of the projection.
 template <typename CamT>
-__device__ __forceinline__ bool normal_kept(const PointOpts& o, const CamT& c, const Proj& p, int64_t i) {
+__device__ __forceinline__ bool normal_kept(const PointOpts& o, const CamT& c, const Proj& p, const PointExtra& e) {
     if (!(o.flags & (kOptCullBack | kOptCullPrinted))) return true;
-    const float nx = o.nx[i], ny = o.ny[i], nz = o.nz[i];
-    const float m0 = __fmaf_rn(c.R[0], nx, __fmaf_rn(c.R[1], ny, __fmul_rn(c.R[2], nz)));
-    const float m1 = __fmaf_rn(c.R[3], nx, __fmaf_rn(c.R[4], ny, __fmul_rn(c.R[5], nz)));
-    const float m2 = __fmaf_rn(c.R[6], nx, __fmaf_rn(c.R[7], ny, __fmul_rn(c.R[8], nz)));
+    const float m0 = __fmaf_rn(c.R[0], e.nx, __fmaf_rn(c.R[1], e.ny, __fmul_rn(c.R[2], e.nz)));
+    const float m1 = __fmaf_rn(c.R[3], e.nx, __fmaf_rn(c.R[4], e.ny, __fmul_rn(c.R[5], e.nz)));
+    const float m2 = __fmaf_rn(c.R[6], e.nx, __fmaf_rn(c.R[7], e.ny, __fmul_rn(c.R[8], e.nz)));
     const float d = __fmaf_rn(m0, p.X, __fmaf_rn(m1, p.Y, __fmul_rn(m2, p.Z)));
     return (o.flags & kOptCullBack) ? d < 0.0f : d > 0.0f;
 }
 
-// Eq. discard for point i: bit l set when the point takes part in layer l,
-// i.e. ((fx r / Z) 2^-l) gamma > sqrt(1 - beta) in FP32 (all bits without
+// Eq. discard: bit l set when the point takes part in layer l, i.e.
+// ((fx r / Z) 2^-l) gamma > sqrt(1 - beta) in FP32 (all bits without
 // discarding).
 template <typename CamT>
-__device__ __forceinline__ uint32_t discard_mask(const PointOpts& o, const CamT& c, const Proj& p, int64_t i, int L) {
+__device__ __forceinline__ uint32_t discard_mask(const PointOpts& o, const CamT& c, const Proj& p, const PointExtra& e,
+                                                 int L) {
     if (!(o.flags & kOptDiscard)) return 0xffu;
-    const float s0 = __fdiv_rn(__fmul_rn(c.fx, o.radius[i]), p.Z);
-    const float rhs = sqrt_rn(__fsub_rn(1.0f, o.beta[i]));
+    const float s0 = __fdiv_rn(__fmul_rn(c.fx, e.r), p.Z);
+    const float rhs = sqrt_rn(__fsub_rn(1.0f, e.beta));
     uint32_t m = 0;
     for (int l = 0; l < L; ++l) m |= (uint32_t)(__fmul_rn(__fmul_rn(s0, layer_scale(l)), o.gamma) > rhs) << l;
     return m;

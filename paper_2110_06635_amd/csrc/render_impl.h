@@ -174,14 +174,14 @@ __device__ __forceinline__ void depth_table_flush(DepthTable& t, uint64_t* __res
 
 template <bool OPTS>
 __device__ __forceinline__ void depth_point(const Cam& c, int L, bool live, float x, float y, float z, uint32_t oi,
-                                            const PointOpts& o, int64_t i, DepthTable* t,
+                                            const PointOpts& o, const PointExtra& e, DepthTable* t,
                                             uint64_t* __restrict__ keys) {
     Proj p = project(c, x, y, z);
     bool ok = live && p.ok;
     uint32_t lmask = 0xffu;
     if (OPTS && o.flags != 0) {   // uniform: culling and discarding read per-point inputs
-        ok = ok && normal_kept(o, c, p, i);
-        if (ok) lmask = discard_mask(o, c, p, i, L);
+        ok = ok && normal_kept(o, c, p, e);
+        if (ok) lmask = discard_mask(o, c, p, e, L);
     }
     uint64_t key = ((uint64_t)__float_as_uint(p.Z) << 32) | oi;
 #if ADOP_DEPTH_TABLE
@@ -253,6 +253,7 @@ __global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_DEPTH_WPE) k_depth(con
     float nx = 0.f, ny = 0.f, nz = 0.f;
     uint32_t noi = 0;
     bool nlive = false;
+    PointExtra ne;
     auto fetch = [&](int64_t c) {
         int64_t i = c * kBlock + threadIdx.x;
         nlive = i < n;
@@ -261,6 +262,7 @@ __global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_DEPTH_WPE) k_depth(con
             ny = ld_nt(ys + i);
             nz = ld_nt(zs + i);
             noi = (uint32_t)ld_nt(orig + i);
+            if (OPTS) load_extra(o, i, ne);
         }
     };
     if (m.c0 < m.c1) fetch(m.c0);
@@ -268,12 +270,12 @@ __global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_DEPTH_WPE) k_depth(con
         const bool live = nlive;
         const float x = nx, y = ny, z = nz;
         const uint32_t oi = noi;
-        const int64_t i = c * kBlock + threadIdx.x;
+        const PointExtra e = ne;
         if (c + 1 < m.c1) fetch(c + 1);
         if (SINGLE) {
-            depth_point<OPTS>(c0, L, live, x, y, z, oi, o, i, t, keys);
+            depth_point<OPTS>(c0, L, live, x, y, z, oi, o, e, t, keys);
         } else {
-            for (int v = 0; v < V; ++v) depth_point<OPTS>(load_cam(views + v), L, live, x, y, z, oi, o, i, t, keys);
+            for (int v = 0; v < V; ++v) depth_point<OPTS>(load_cam(views + v), L, live, x, y, z, oi, o, e, t, keys);
         }
     }
 #if ADOP_DEPTH_TABLE
@@ -467,15 +469,15 @@ template <int C, bool OPTS>
 #define ADOP_WC_ARG
 #endif
 __device__ __forceinline__ void accum_point(const Cam& c, int L, float fa, bool live, float x, float y, float z,
-                                            const float (&f)[C], const PointOpts& o, int64_t i,
+                                            const float (&f)[C], const PointOpts& o, const PointExtra& e,
                                             const uint32_t* __restrict__ keys32, AccTable<C>& t,
                                             float* __restrict__ sums, int32_t* __restrict__ counts ADOP_WC_PARAM) {
     Proj p = project(c, x, y, z);
     bool ok = live && p.ok;
     uint32_t lmask = 0xffu;
     if (OPTS && (o.flags & (kOptCullBack | kOptCullPrinted | kOptDiscard))) {
-        ok = ok && normal_kept(o, c, p, i);
-        if (ok) lmask = discard_mask(o, c, p, i, L);
+        ok = ok && normal_kept(o, c, p, e);
+        if (ok) lmask = discard_mask(o, c, p, e, L);
     }
     // all layers' front depths are gathered before any update, so the
     // gathers are in flight together
@@ -528,6 +530,7 @@ __global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_ACCUM_WPE) k_accum(con
 #pragma unroll
     for (int ch = 0; ch < C; ++ch) nf[ch] = 0.f;
     bool nlive = false;
+    PointExtra ne;
     auto fetch = [&](int64_t c) {
         int64_t i = c * kBlock + threadIdx.x;
         nlive = i < n;
@@ -536,6 +539,7 @@ __global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_ACCUM_WPE) k_accum(con
             ny = ld_nt(ys + i);
             nz = ld_nt(zs + i);
             load_feat<C, S>(feat, i, nf);
+            if (OPTS) load_extra(o, i, ne);
         }
     };
     if (m.c0 < m.c1) fetch(m.c0);
@@ -545,13 +549,13 @@ __global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_ACCUM_WPE) k_accum(con
         float f[C];
 #pragma unroll
         for (int ch = 0; ch < C; ++ch) f[ch] = nf[ch];
+        const PointExtra e = ne;
         if (c + 1 < m.c1) fetch(c + 1);
         if (OPTS && (o.flags & kOptLog)) {
 #pragma unroll
             for (int ch = 0; ch < C; ++ch) f[ch] = expf(f[ch]);
         }
-        accum_point<C, OPTS>(c0, L, fa, live, x, y, z, f, o, c * kBlock + threadIdx.x, keys32, t, sums,
-                       counts ADOP_WC_ARG);
+        accum_point<C, OPTS>(c0, L, fa, live, x, y, z, f, o, e, keys32, t, sums, counts ADOP_WC_ARG);
         if (kAccWindow > 0 && ++since == kAccWindow) {   // uniform in the workgroup
             since = 0;
             __syncthreads();
@@ -711,14 +715,14 @@ template <int C, bool OPTS>
 __device__ __forceinline__ void point_view(const Cam& c, int L, float fa, bool spatial_all,
                                            const float* __restrict__ pack, bool live, float x, float y, float z,
                                            const float (&tau)[C], float (&dt)[C], float (&dp)[3], float (&acc)[15],
-                                           bool& any, const PointOpts& o, int64_t i) {
+                                           bool& any, const PointOpts& o, const PointExtra& e) {
     using PL = PackLayout<C>;
     Proj p = project(c, x, y, z);
     if (!(live && p.ok)) return;
     uint32_t lmask = 0xffu;
     if (OPTS && (o.flags & (kOptCullBack | kOptCullPrinted | kOptDiscard))) {
-        if (!normal_kept(o, c, p, i)) return;
-        lmask = discard_mask(o, c, p, i, L);
+        if (!normal_kept(o, c, p, e)) return;
+        lmask = discard_mask(o, c, p, e, L);
     }
     float gu = 0.f, gv = 0.f;
     // bit l of work: the layer needs the neighbour records; bit l of seen:
@@ -839,6 +843,7 @@ __global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_BWD_WPE) k_backward(co
         float px_[PPL], py_[PPL], pz_[PPL];
         float tau[PPL][C], dt[PPL][C], dp[PPL][3];
         bool live[PPL];
+        PointExtra ex[PPL];
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
             int64_t i = wbase + (int64_t)k * kWave + lane;
@@ -852,6 +857,7 @@ __global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_BWD_WPE) k_backward(co
                 py_[k] = ld_nt(ys + i);
                 pz_[k] = ld_nt(zs + i);
                 load_feat<C, S>(feat, i, tau[k]);
+                if (OPTS) load_extra(o, i, ex[k]);
             }
             if (OPTS && (o.flags & kOptLog)) {   // logarithmic descriptors render as exp(f)
 #pragma unroll
@@ -863,7 +869,7 @@ __global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_BWD_WPE) k_backward(co
 #pragma unroll
             for (int k = 0; k < PPL; ++k)
                 point_view<C, OPTS>(c0, L, fa, spatial_all, pack, live[k], px_[k], py_[k], pz_[k], tau[k], dt[k], dp[k],
-                              acc1, any, o, wbase + (int64_t)k * kWave + lane);
+                              acc1, any, o, ex[k]);
             if (++since == kSuper || c + 1 == m.c1) {
                 double* slot = acc_lds + threadIdx.x * 16;
 #pragma unroll
@@ -883,7 +889,7 @@ __global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_BWD_WPE) k_backward(co
 #pragma unroll
                 for (int k = 0; k < PPL; ++k)
                     point_view<C, OPTS>(cv, L, fa, spatial_all, pack, live[k], px_[k], py_[k], pz_[k], tau[k], dt[k],
-                                  dp[k], acc, any, o, wbase + (int64_t)k * kWave + lane);
+                                  dp[k], acc, any, o, ex[k]);
                 reduce_terms(acc, any, acc_lds + (wave * V + v) * 16, lane);
             }
         }
