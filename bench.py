@@ -31,7 +31,8 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ["paper_2110_06635_amd/csrc/render.hip", "paper_2110_06635_amd/csrc/device.h",
+KERNEL_SOURCES = ["paper_2110_06635_amd/csrc/render_impl.h", "paper_2110_06635_amd/csrc/render.hip",
+                  "paper_2110_06635_amd/csrc/render_c1.hip", "paper_2110_06635_amd/csrc/device.h",
                   "paper_2110_06635_amd/csrc/launch.h"]
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 

@@ -33,63 +33,12 @@
 
 namespace adop {
 
-#ifndef ADOP_MAX_GROUPS
-#define ADOP_MAX_GROUPS 6
-#endif
-#ifndef ADOP_MIN_GROUP
-#define ADOP_MIN_GROUP 3
-#endif
+// bits of the accumulation's per-workgroup LDS table for up to 4 channels
+// (one less for 5..8, two less for 9..16)
 #ifndef ADOP_ACC_BITS4
 #define ADOP_ACC_BITS4 9
 #endif
-#ifndef ADOP_DEPTH_BITS
-#define ADOP_DEPTH_BITS 12
-#endif
-#ifndef ADOP_DEPTH_WAVEMIN
-#define ADOP_DEPTH_WAVEMIN 1
-#endif
-// ADOP_DEPTH_TABLE 1: LDS table per workgroup; 0 (default, faster on the
-// benchmark scene): read the global keys of all layers first, then compare
-// and issue the (rare) atomic minimum
-#ifndef ADOP_DEPTH_TABLE
-#define ADOP_DEPTH_TABLE 0
-#endif
-// ADOP_ACC_TABLE 1: LDS table per workgroup; 0: wave groups go straight to
-// global atomics
-#ifndef ADOP_ACC_TABLE
-#define ADOP_ACC_TABLE 1
-#endif
-// minimum waves per SIMD the point kernels are compiled for (bounds their
-// register use); 0 leaves the choice to the compiler
-#ifndef ADOP_DEPTH_WPE
-#define ADOP_DEPTH_WPE 0
-#endif
-#ifndef ADOP_ACCUM_WPE
-#define ADOP_ACCUM_WPE 0
-#endif
-#ifndef ADOP_BWD_WPE
-#define ADOP_BWD_WPE 0
-#endif
-#define ADOP_WPE_ATTR(n) __attribute__((amdgpu_waves_per_eu((n) > 0 ? (n) : 1)))
-// ADOP_ACC_WCACHE 1: per-wave register cache of 64 pixel sums in front of
-// the workgroup table
-#ifndef ADOP_ACC_WCACHE
-#define ADOP_ACC_WCACHE 1
-#endif
-// ADOP_DEPTH_RUNS 1: the same for the depth pass (segmented minima)
-#ifndef ADOP_DEPTH_RUNS
-#define ADOP_DEPTH_RUNS 1
-#endif
-// chunks between write-outs of the accumulation's workgroup table (0: only
-// at the end of the workgroup's range)
-#ifndef ADOP_ACC_WINDOW
-#define ADOP_ACC_WINDOW 0
-#endif
-// ADOP_ACC_RUNS 1: a wave whose passing points fall into several pixels
-// sums runs of equal pixels with a segmented DPP scan instead of grouping
-#ifndef ADOP_ACC_RUNS
-#define ADOP_ACC_RUNS 1
-#endif
+// points per lane of the backward pass for up to 4 channels
 #ifndef ADOP_PPL4
 #define ADOP_PPL4 4
 #endif
@@ -116,65 +65,9 @@ __global__ void __launch_bounds__(256) k_clear(uint64_t* __restrict__ keys, int3
 #endif  // ADOP_RENDER_BASE
 
 // ---- depth pass -----------------------------------------------------------
-constexpr int kDepthBits = ADOP_DEPTH_BITS;
-constexpr int kDepthH = 1 << kDepthBits;
-
-struct DepthTable {
-    uint32_t key[kDepthH];
-    uint64_t val[kDepthH];
-};
-
-__device__ __forceinline__ void global_min(uint64_t* __restrict__ gkeys, uint32_t pix, uint64_t k) {
-    uint64_t cur = load_relaxed_u64(gkeys + pix);
-    if (k < cur) atomic_min_u64(gkeys + pix, k);
-}
-
-// Lower the pixel's minimum to k: read first, update only when it would
-// lower the value (keys only decrease, so a stale read can only let an
-// unnecessary atomic through).
-__device__ __forceinline__ void table_min(DepthTable& t, uint64_t* __restrict__ gkeys, uint32_t pix, uint64_t k) {
-    int slot = table_slot2<kDepthBits>(t.key, pix);
-    if (slot < 0) {
-        global_min(gkeys, pix, k);
-        return;
-    }
-    uint64_t cur = __hip_atomic_load(&t.val[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (k < cur) __hip_atomic_fetch_min(&t.val[slot], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-__device__ __forceinline__ void depth_update(bool in, uint32_t pix, uint64_t key, DepthTable& t,
-                                             uint64_t* __restrict__ gkeys) {
-#if ADOP_DEPTH_WAVEMIN
-    uint64_t m = ballot(in);
-    if (m == 0) return;
-    int leader = __builtin_ctzll(m);
-    uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pix, leader);
-    if (ballot(in && pix != p0) == 0) {
-        uint64_t k = wave_min_u64(in ? key : ~0ull);
-        if (lane_id() == leader) table_min(t, gkeys, p0, k);
-        return;
-    }
-#endif
-    if (in) table_min(t, gkeys, pix, key);
-}
-
-__device__ __forceinline__ void depth_table_clear(DepthTable& t) {
-    for (int j = threadIdx.x; j < kDepthH; j += blockDim.x) {
-        t.key[j] = kEmptySlot;
-        t.val[j] = ~0ull;
-    }
-}
-
-__device__ __forceinline__ void depth_table_flush(DepthTable& t, uint64_t* __restrict__ gkeys) {
-    for (int j = threadIdx.x; j < kDepthH; j += blockDim.x) {
-        uint32_t k = t.key[j];
-        if (k != kEmptySlot) global_min(gkeys, k, t.val[j]);
-    }
-}
-
 template <bool OPTS>
 __device__ __forceinline__ void depth_point(const Cam& c, int L, bool live, float x, float y, float z, uint32_t oi,
-                                            const PointOpts& o, const PointExtra& e, DepthTable* t,
+                                            const PointOpts& o, const PointExtra& e,
                                             uint64_t* __restrict__ keys) {
     Proj p = project(c, x, y, z);
     bool ok = live && p.ok;
@@ -184,16 +77,6 @@ __device__ __forceinline__ void depth_point(const Cam& c, int L, bool live, floa
         if (ok) lmask = discard_mask(o, c, p, e, L);
     }
     uint64_t key = ((uint64_t)__float_as_uint(p.Z) << 32) | oi;
-#if ADOP_DEPTH_TABLE
-#pragma unroll
-    for (int l = 0; l < kMaxLayers; ++l) {
-        if (l >= L) break;
-        int px = 0, py = 0;
-        uint32_t pix = 0;
-        bool in = layer_pixel(c, ok, l, p.u0, p.v0, px, py, pix) && ((lmask >> l) & 1u);
-        depth_update(in, pix, key, *t, keys);
-    }
-#else
     uint32_t pix[kMaxLayers];
     bool in[kMaxLayers];
     uint64_t cur[kMaxLayers];
@@ -220,33 +103,20 @@ __device__ __forceinline__ void depth_point(const Cam& c, int L, bool live, floa
             uint64_t k = wave_min_u64(want ? key : ~0ull);
             if (lane_id() == leader) atomic_min_u64(keys + p0, k);
         } else {
-#if ADOP_DEPTH_RUNS
             // several pixels: segmented minima over runs of equal pixels
             uint64_t k = want ? key : ~0ull;
             if (run_min_u64(want ? pix[l] : kEmptySlot, kEmptySlot, k)) atomic_min_u64(keys + pix[l], k);
-#else
-            if (want) atomic_min_u64(keys + pix[l], key);
-#endif
         }
     }
-#endif
 }
 
 #ifdef ADOP_RENDER_BASE
 // OPTS: compiled with the optional per-point inputs (culling, discarding)
 template <bool SINGLE, bool OPTS>
-__global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_DEPTH_WPE) k_depth(const float* __restrict__ xs, const float* __restrict__ ys,
+__global__ void __launch_bounds__(256) k_depth(const float* __restrict__ xs, const float* __restrict__ ys,
                                                const float* __restrict__ zs, const int32_t* __restrict__ orig,
                                                int64_t n, const ViewRec* __restrict__ views, int V, int L,
                                                PointOpts o, uint64_t* __restrict__ keys) {
-#if ADOP_DEPTH_TABLE
-    __shared__ DepthTable table;
-    DepthTable* t = &table;
-    depth_table_clear(table);
-    __syncthreads();
-#else
-    DepthTable* t = nullptr;
-#endif
     const Cam c0 = load_cam(views);
     RangeMap m = range_map(n, kBlock);
     // the next chunk's points are loaded while the current one is processed
@@ -273,25 +143,18 @@ __global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_DEPTH_WPE) k_depth(con
         const PointExtra e = ne;
         if (c + 1 < m.c1) fetch(c + 1);
         if (SINGLE) {
-            depth_point<OPTS>(c0, L, live, x, y, z, oi, o, e, t, keys);
+            depth_point<OPTS>(c0, L, live, x, y, z, oi, o, e, keys);
         } else {
-            for (int v = 0; v < V; ++v) depth_point<OPTS>(load_cam(views + v), L, live, x, y, z, oi, o, e, t, keys);
+            for (int v = 0; v < V; ++v) depth_point<OPTS>(load_cam(views + v), L, live, x, y, z, oi, o, e, keys);
         }
     }
-#if ADOP_DEPTH_TABLE
-    __syncthreads();
-    depth_table_flush(table, keys);
-#endif
 }
 #endif  // ADOP_RENDER_BASE
 
 // ---- accumulation pass ----------------------------------------------------
-constexpr int kAccWindow = ADOP_ACC_WINDOW;
-constexpr int kMaxGroups = ADOP_MAX_GROUPS;
-constexpr int kMinGroup = ADOP_MIN_GROUP;
 
 template <int C> struct AccTable {
-    static constexpr int bits = !ADOP_ACC_TABLE ? 1 : C <= 4 ? ADOP_ACC_BITS4 : (C <= 8 ? ADOP_ACC_BITS4 - 1 : ADOP_ACC_BITS4 - 2);
+    static constexpr int bits = C <= 4 ? ADOP_ACC_BITS4 : (C <= 8 ? ADOP_ACC_BITS4 - 1 : ADOP_ACC_BITS4 - 2);
     static constexpr int H = 1 << bits;
     uint32_t key[H];
     float sum[C][H];
@@ -301,7 +164,7 @@ template <int C> struct AccTable {
 template <int C>
 __device__ __forceinline__ void table_add(AccTable<C>& t, float* __restrict__ sums, int32_t* __restrict__ counts,
                                           uint32_t pix, const float (&s)[C], int32_t k) {
-    int slot = ADOP_ACC_TABLE ? table_slot2<AccTable<C>::bits>(t.key, pix) : -1;
+    int slot = table_slot2<AccTable<C>::bits>(t.key, pix);
     if (slot < 0) {
         float* dst = sums + (uint64_t)pix * C;
 #pragma unroll
@@ -363,72 +226,36 @@ __device__ __forceinline__ void wcache_flush(WaveCache<C>& w, AccTable<C>& t, fl
     wcache_init<C>(w);
 }
 
-// Lanes whose point passes are grouped by pixel: the first remaining lane's
-// pixel, the ballot of the lanes sharing it, DPP sums; groups smaller than
-// kMinGroup (and lanes left after kMaxGroups) add individually.
+// Passing lanes that all fall into one pixel: one wave sum into the wave
+// cache; otherwise segmented sums over runs of equal pixels (consecutive
+// lanes), one table update per run.
 template <int C>
 __device__ __forceinline__ void accum_update(bool pass, uint32_t pix, const float (&f)[C], AccTable<C>& t,
-                                             float* __restrict__ sums, int32_t* __restrict__ counts
-#if ADOP_ACC_WCACHE
-                                             , WaveCache<C>& w
-#endif
-                                             ) {
-    uint64_t rem = ballot(pass);
+                                             float* __restrict__ sums, int32_t* __restrict__ counts,
+                                             WaveCache<C>& w) {
+    const uint64_t rem = ballot(pass);
     if (rem == 0) return;
-    const int lane = lane_id();
-#if ADOP_ACC_RUNS
-    {
-        // one pixel for every passing lane: one wave sum; otherwise segmented
-        // sums over runs of equal pixels, one update per run
-        const int leader = __builtin_ctzll(rem);
-        const uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pix, leader);
-        const uint64_t mm = ballot(pass && pix == p0);
-        if (mm == rem) {
-            float s[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) s[c] = pass ? f[c] : 0.0f;
-            wave_sum_n<C>(s);
-            const int k = __builtin_popcountll(mm);
-#if ADOP_ACC_WCACHE
-            wcache_add<C>(w, p0, s, k, t, sums, counts);
-#else
-            if (lane == leader) table_add<C>(t, sums, counts, p0, s, k);
-#endif
-            return;
-        }
-        float v[C + 1];
-#pragma unroll
-        for (int c = 0; c < C; ++c) v[c] = pass ? f[c] : 0.0f;
-        v[C] = pass ? 1.0f : 0.0f;
-        if (run_sums<C + 1>(pass ? pix : kEmptySlot, kEmptySlot, v)) {
-            float s[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) s[c] = v[c];
-            table_add<C>(t, sums, counts, pix, s, (int32_t)v[C]);
-        }
-        return;
-    }
-#endif
-#pragma unroll 1
-    for (int it = 0; it < kMaxGroups && rem != 0; ++it) {
-        int leader = __builtin_ctzll(rem);
-        uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pix, leader);
-        uint64_t mm = ballot(pass && pix == p0);
-        int k = __builtin_popcountll(mm);
-        if (k < kMinGroup) break;
-        bool mine = (mm >> lane) & 1;
+    const int leader = __builtin_ctzll(rem);
+    const uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pix, leader);
+    const uint64_t mm = ballot(pass && pix == p0);
+    if (mm == rem) {
         float s[C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) s[c] = mine ? f[c] : 0.0f;
+        for (int c = 0; c < C; ++c) s[c] = pass ? f[c] : 0.0f;
         wave_sum_n<C>(s);
-#if ADOP_ACC_WCACHE
-        wcache_add<C>(w, p0, s, k, t, sums, counts);
-#else
-        if (lane == leader) table_add<C>(t, sums, counts, p0, s, k);
-#endif
-        rem &= ~mm;
+        wcache_add<C>(w, p0, s, __builtin_popcountll(mm), t, sums, counts);
+        return;
     }
-    if ((rem >> lane) & 1) table_add<C>(t, sums, counts, pix, f, 1);
+    float v[C + 1];
+#pragma unroll
+    for (int c = 0; c < C; ++c) v[c] = pass ? f[c] : 0.0f;
+    v[C] = pass ? 1.0f : 0.0f;
+    if (run_sums<C + 1>(pass ? pix : kEmptySlot, kEmptySlot, v)) {
+        float s[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) s[c] = v[c];
+        table_add<C>(t, sums, counts, pix, s, (int32_t)v[C]);
+    }
 }
 
 template <int C>
@@ -461,17 +288,10 @@ __device__ __forceinline__ void acc_table_flush(AccTable<C>& t, float* __restric
 }
 
 template <int C, bool OPTS>
-#if ADOP_ACC_WCACHE
-#define ADOP_WC_PARAM , WaveCache<C>& w
-#define ADOP_WC_ARG , w
-#else
-#define ADOP_WC_PARAM
-#define ADOP_WC_ARG
-#endif
 __device__ __forceinline__ void accum_point(const Cam& c, int L, float fa, bool live, float x, float y, float z,
                                             const float (&f)[C], const PointOpts& o, const PointExtra& e,
                                             const uint32_t* __restrict__ keys32, AccTable<C>& t,
-                                            float* __restrict__ sums, int32_t* __restrict__ counts ADOP_WC_PARAM) {
+                                            float* __restrict__ sums, int32_t* __restrict__ counts, WaveCache<C>& w) {
     Proj p = project(c, x, y, z);
     bool ok = live && p.ok;
     uint32_t lmask = 0xffu;
@@ -499,17 +319,16 @@ __device__ __forceinline__ void accum_point(const Cam& c, int L, float fa, bool 
     for (int l = 0; l < kMaxLayers; ++l) {
         if (l >= L) break;
         bool pass = in[l] && p.Z <= __fmul_rn(mz[l], fa);
-        accum_update<C>(pass, pix[l], f, t, sums, counts ADOP_WC_ARG);
+        accum_update<C>(pass, pix[l], f, t, sums, counts, w);
     }
 }
 
 // One view per workgroup: with V views the grid holds V workgroups per
 // point range (view = block % V), so every workgroup's table and wave cache
 // see one view's pixels; the V workgroups of a range are dispatched together
-// and read its points while they are in the caches.  The workgroup table is
-// written out every kAccWindow chunks, before it fills.
+// and read its points while they are in the caches.
 template <int C, typename S, bool OPTS>
-__global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_ACCUM_WPE) k_accum(const float* __restrict__ xs, const float* __restrict__ ys,
+__global__ void __launch_bounds__(256) k_accum(const float* __restrict__ xs, const float* __restrict__ ys,
                                                const float* __restrict__ zs, const void* __restrict__ feat,
                                                int64_t n, const ViewRec* __restrict__ views, int V, int L,
                                                float fa, PointOpts o, const uint32_t* __restrict__ keys32,
@@ -517,14 +336,11 @@ __global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_ACCUM_WPE) k_accum(con
     __shared__ AccTable<C> t;
     acc_table_clear<C>(t);
     __syncthreads();
-#if ADOP_ACC_WCACHE
     WaveCache<C> w;
     wcache_init<C>(w);
-#endif
     const int view = V > 1 ? (int)(blockIdx.x % (unsigned)V) : 0;
     const Cam c0 = load_cam(views + view);
     RangeMap m = V > 1 ? range_map_views(n, kBlock, V) : range_map(n, kBlock);
-    int since = 0;
     // the next chunk's points are loaded while the current one is processed
     float nx = 0.f, ny = 0.f, nz = 0.f, nf[C];
 #pragma unroll
@@ -555,17 +371,9 @@ __global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_ACCUM_WPE) k_accum(con
 #pragma unroll
             for (int ch = 0; ch < C; ++ch) f[ch] = expf(f[ch]);
         }
-        accum_point<C, OPTS>(c0, L, fa, live, x, y, z, f, o, e, keys32, t, sums, counts ADOP_WC_ARG);
-        if (kAccWindow > 0 && ++since == kAccWindow) {   // uniform in the workgroup
-            since = 0;
-            __syncthreads();
-            acc_table_flush<C>(t, sums, counts);
-            __syncthreads();
-        }
+        accum_point<C, OPTS>(c0, L, fa, live, x, y, z, f, o, e, keys32, t, sums, counts, w);
     }
-#if ADOP_ACC_WCACHE
     wcache_flush<C>(w, t, sums, counts);
-#endif
     __syncthreads();
     acc_table_flush<C>(t, sums, counts);
 }
@@ -815,7 +623,7 @@ __device__ __forceinline__ void reduce_terms(const float (&acc)[15], bool any, d
 constexpr int kSuper = 4;   // chunks a lane sums in FP32 before widening (single view)
 
 template <int C, typename S, int PPL, bool SINGLE, bool OPTS>
-__global__ void __launch_bounds__(256) ADOP_WPE_ATTR(ADOP_BWD_WPE) k_backward(const float* __restrict__ xs, const float* __restrict__ ys,
+__global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, const float* __restrict__ ys,
                                                   const float* __restrict__ zs, const void* __restrict__ feat,
                                                   int64_t n, const ViewRec* __restrict__ views, int V, int L,
                                                   float fa, uint32_t flags, PointOpts o,
