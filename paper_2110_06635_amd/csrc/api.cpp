@@ -134,14 +134,14 @@ int64_t max_layer_pixels(const adop_camera* cams, int32_t V) {
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
-int bwd_group_cap(int cus) { return std::max(8, cus * 4 / 8 * 8); }
+int bwd_group_cap(int cus) { return std::max(8, cus * adop::kBwdGroupsPerCu / 8 * 8); }
 
 size_t views_region(int32_t V) { return align256((size_t)std::max(V, 1) * sizeof(ViewRec)); }
 
 size_t workspace_bytes(int cus, int32_t C, int32_t V, int64_t pixels) {
     size_t fwd = (size_t)pixels * C * sizeof(float);
     size_t bwd = align256((size_t)pixels * adop::pack_stride(C) * sizeof(float)) +
-                 (size_t)bwd_group_cap(cus) * std::max(V, 1) * 16 * sizeof(double);
+                 (size_t)(bwd_group_cap(cus) + adop::kReduceSlices) * std::max(V, 1) * 16 * sizeof(double);
     return views_region(V) + align256(std::max(fwd, bwd));
 }
 
@@ -506,6 +506,7 @@ adop_status adop_render_backward(adop_context* ctx, const adop_scene* scene, con
     unsigned char* wsb = static_cast<unsigned char*>(workspace) + views_region(V);
     a.pack = reinterpret_cast<float*>(wsb);
     a.partials = reinterpret_cast<double*>(wsb + align256((size_t)total * adop::pack_stride(a.C) * sizeof(float)));
+    a.slices = a.partials + (size_t)a.groups * V * 16;
     a.dfeat = dfeat;
     a.dpos = dpos;
     a.dpose = dpose;

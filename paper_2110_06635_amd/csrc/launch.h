@@ -52,6 +52,13 @@ struct FwdArgs {
     Timer timer;
 };
 
+// The FP64 pose/intrinsics partials of the backward workgroups are summed
+// in two fixed-order stages: kReduceSlices contiguous slices per view, then
+// the slices.
+constexpr int kReduceSlices = 64;
+// Largest backward grid per CU (the partials buffer is sized for it).
+constexpr int kBwdGroupsPerCu = 128;
+
 struct BwdArgs {
     int dtype, C, V, L, cus, groups;   // groups: largest backward grid the partials buffer holds
     uint32_t flags;
@@ -67,6 +74,7 @@ struct BwdArgs {
     PointOpts opts;
     float* pack;       // workspace [pixels][stride]
     double* partials;  // workspace [groups][V][16]
+    double* slices;    // workspace [V][kReduceSlices][16]
     float* dfeat;
     float* dpos;
     double* dpose;

@@ -16,7 +16,8 @@ void launch_clear(const FwdArgs& a, int64_t nsums, hipStream_t st) {
 template <bool SINGLE, bool OPTS>
 static void depth_pass(const FwdArgs& a, hipStream_t st) {
     static const int occ = resident(k_depth<SINGLE, OPTS>, 0);
-    const unsigned gd = persistent_grid(a.n, kBlock, a.cus, occ, 1 << 20);
+    unsigned gd = persistent_grid(a.n, kBlock, a.cus, occ, 1 << 20);
+    if (!SINGLE) gd = range_grid(a.n, kDepthViewRange, gd);
     k_depth<SINGLE, OPTS><<<gd, kBlock, 0, st>>>(a.x, a.y, a.z, a.orig, a.n, a.views, a.V, a.L, a.opts, a.keys);
 }
 
@@ -30,7 +31,8 @@ void launch_depth(const FwdArgs& a, hipStream_t st) {
 
 void launch_reduce(const BwdArgs& a, unsigned groups, hipStream_t st) {
     a.timer.mark(kKReduce, 0, st);
-    k_reduce<<<a.V, 256, 0, st>>>(a.partials, (int)groups, a.V, a.dpose, a.dintr);
+    k_reduce_slices<<<dim3(kReduceSlices, (unsigned)a.V), 256, 0, st>>>(a.partials, (int)groups, a.V, a.slices);
+    k_reduce<<<a.V, 64, 0, st>>>(a.slices, a.dpose, a.dintr);
     a.timer.mark(kKReduce, 1, st);
 }
 

@@ -17,7 +17,8 @@
 //                gradp, spatialderiv), chain to positions, pose (Eq. tangent)
 //                and intrinsics; per-point terms in FP32, pose/intrinsics
 //                sums in FP64 with a fixed reduction order
-//   k_reduce     fixed-order FP64 sum of the per-workgroup partials
+//   k_reduce_slices, k_reduce   fixed-order FP64 sum of the per-workgroup
+//                partials (slices of workgroups, then the slices)
 //
 // Every workgroup of a point kernel owns one contiguous range of the
 // Morton-ordered points (a compact region of space), so the 64 points of a
@@ -739,19 +740,28 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
     }
 }
 
-// Fixed-order FP64 sum over workgroup partials; block v writes view v.
+// Fixed-order FP64 sums over the workgroup partials, in two stages.
+// Stage 1: block (s, v) sums groups [s G / S, (s+1) G / S) of view v
+// (S = kReduceSlices): each thread a strided subset in order, then a tree
+// over the threads.
 #ifdef ADOP_RENDER_BASE
-__global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ partials, int groups, int V,
-                                                double* __restrict__ dpose, double* __restrict__ dintr) {
+__global__ void __launch_bounds__(256) k_reduce_slices(const double* __restrict__ partials, int groups, int V,
+                                                       double* __restrict__ slices) {
     __shared__ double red[256][16];
-    int v = blockIdx.x;
+    const int sl = blockIdx.x, v = blockIdx.y;
+    const int g0 = (int)((int64_t)groups * sl / kReduceSlices);
+    const int g1 = (int)((int64_t)groups * (sl + 1) / kReduceSlices);
     double s[16];
 #pragma unroll
     for (int t = 0; t < 16; ++t) s[t] = 0.0;
-    for (int g = threadIdx.x; g < groups; g += blockDim.x) {
-        const double* p = partials + ((uint64_t)g * V + v) * 16;
+    for (int g = g0 + (int)threadIdx.x; g < g1; g += blockDim.x) {
+        const double2* p = reinterpret_cast<const double2*>(partials + ((uint64_t)g * V + v) * 16);
 #pragma unroll
-        for (int t = 0; t < 16; ++t) s[t] += p[t];
+        for (int t = 0; t < 8; ++t) {
+            const double2 d = p[t];
+            s[2 * t] += d.x;
+            s[2 * t + 1] += d.y;
+        }
     }
 #pragma unroll
     for (int t = 0; t < 16; ++t) red[threadIdx.x][t] = s[t];
@@ -763,8 +773,18 @@ __global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ parti
         }
         __syncthreads();
     }
-    if (threadIdx.x < 6) dpose[v * 6 + threadIdx.x] = red[0][threadIdx.x];
-    else if (threadIdx.x < 15) dintr[v * 9 + threadIdx.x - 6] = red[0][threadIdx.x];
+    if (threadIdx.x < 16) slices[((uint64_t)v * kReduceSlices + sl) * 16 + threadIdx.x] = red[0][threadIdx.x];
+}
+
+// Stage 2: block v sums its slices in order; writes dpose[v], dintr[v].
+__global__ void __launch_bounds__(64) k_reduce(const double* __restrict__ slices, double* __restrict__ dpose,
+                                               double* __restrict__ dintr) {
+    const int v = blockIdx.x, t = threadIdx.x;
+    if (t >= 15) return;
+    double r = 0.0;
+    for (int sl = 0; sl < kReduceSlices; ++sl) r += slices[((uint64_t)v * kReduceSlices + sl) * 16 + t];
+    if (t < 6) dpose[v * 6 + t] = r;
+    else dintr[v * 9 + t - 6] = r;
 }
 #endif  // ADOP_RENDER_BASE
 
@@ -807,6 +827,25 @@ static inline unsigned persistent_grid(int64_t n, int64_t chunk, int cus, int pe
     return (unsigned)g;
 }
 
+// Points per workgroup (one contiguous range of the Morton order each).
+// The cost of a point varies by orders of magnitude across the scene (a
+// dense cluster front blends and gathers at every layer, empty space only
+// projects), so an even split over the resident workgroups leaves a long
+// tail; ranges far smaller than that split let the hardware dispatcher
+// balance the load.  The single-view depth pass, whose cost per point is
+// nearly uniform, keeps the persistent split.
+constexpr int64_t kAccumRange = 4096;       // accumulation, one view
+constexpr int64_t kAccumViewRange = 2048;   // accumulation, per workgroup of one of several views
+constexpr int64_t kDepthViewRange = 4096;   // depth pass, several views
+constexpr int64_t kBackwardRange = 4096;    // backward
+
+// Grid of ranges of `range` points, a multiple of 8 and at least at_least.
+static inline unsigned range_grid(int64_t n, int64_t range, unsigned at_least) {
+    int64_t g = (n + range - 1) / range;
+    g = (g + kXcds - 1) / kXcds * kXcds;
+    return (unsigned)std::max<int64_t>(g, at_least);
+}
+
 // Kernels that do not depend on the channel count or storage type are
 // compiled once (render.hip); the channel-specific translation units launch
 // them through these functions.
@@ -818,10 +857,13 @@ template <int C, typename S, bool SINGLE, bool OPTS>
 static void forward_points(const FwdArgs& a, hipStream_t st) {
     static const int occ_accum = resident(k_accum<C, S, OPTS>, 0);
     launch_depth(a, st);
-    unsigned ga = persistent_grid(a.n, kBlock, a.cus, occ_accum, 1 << 20);
-    if (!SINGLE) {
+    unsigned ga;
+    if (SINGLE) {
+        ga = range_grid(a.n, kAccumRange, persistent_grid(a.n, kBlock, a.cus, occ_accum, 1 << 20));
+    } else {
         // V workgroups (one per view) per point range
-        int64_t ranges = std::max<int64_t>(kXcds, (int64_t)ga / a.V / kXcds * kXcds);
+        const unsigned per_view = persistent_grid(a.n, kBlock, a.cus, occ_accum, 1 << 20) / (unsigned)a.V;
+        int64_t ranges = range_grid(a.n, kAccumViewRange, per_view);
         ranges = std::min<int64_t>(ranges, (a.n + kBlock - 1) / kBlock);
         ga = (unsigned)(std::max<int64_t>(ranges, 1) * a.V);
     }
@@ -853,6 +895,7 @@ static unsigned backward_points(const BwdArgs& a, hipStream_t st) {
     static const int occ = resident(k_backward<C, S, PPL, SINGLE, OPTS>,
                                     SINGLE ? lds : (size_t)4 * kMaxViewsBwd * 16 * sizeof(double));
     unsigned g = persistent_grid(a.n, (int64_t)kBlock * PPL, a.cus, occ, a.groups);
+    g = std::min<unsigned>(range_grid(a.n, kBackwardRange, g), (unsigned)a.groups / kXcds * kXcds);
     a.timer.mark(kKBackward, 0, st);
     k_backward<C, S, PPL, SINGLE, OPTS><<<g, kBlock, lds, st>>>(a.x, a.y, a.z, a.feat, a.n, a.views, a.V, a.L, a.fa,
                                                           a.flags, a.opts, a.pack, a.dfeat, a.dpos, a.partials);
