@@ -479,15 +479,30 @@ __device__ __forceinline__ RangeMap range_map(int64_t n, int64_t chunk) {
     return m;
 }
 
-// Several views, one per workgroup: workgroup b renders view b % V of point
-// range b / V; the ranges are contiguous and in dispatch order.
-__device__ __forceinline__ RangeMap range_map_views(int64_t n, int64_t chunk, int V) {
+// Several views, one per workgroup.  The grid holds R point ranges for each
+// of the V views (R a multiple of 8), dispatched in groups of VG views: the
+// blocks of group g render views g VG .. g VG + VG - 1 (fewer in the last
+// group), interleaved, so each view's blocks are spread evenly over the 8
+// XCDs, and within a view the ranges of one XCD are a contiguous share of
+// the Morton order.  The views of a group share the dispatch window, so the
+// caches hold one group's per-pixel buffers while its points stream by.
+__device__ __forceinline__ RangeMap view_range_map(int64_t n, int64_t chunk, int V, int VG, int& view) {
     RangeMap m;
     const int64_t nc = (n + chunk - 1) / chunk;
-    const int64_t G = (int64_t)(gridDim.x / (unsigned)V);
-    const int64_t g = (int64_t)(blockIdx.x / (unsigned)V);
-    m.c0 = nc * g / G;
-    m.c1 = nc * (g + 1) / G;
+    const int64_t R = (int64_t)gridDim.x / V;
+    const int64_t b = blockIdx.x;
+    const int64_t g = b / (R * VG);
+    const int64_t w = b - g * R * VG;
+    const int64_t gs = (V - g * VG) < VG ? (V - g * VG) : VG;   // views in this group
+    view = (int)(g * VG + w % gs);
+    const int64_t rr = w / gs;                               // range index in dispatch order
+    int64_t r = rr;
+    if (gs <= kXcds && kXcds % gs == 0) {
+        const int64_t per = kXcds / gs;                      // XCDs that share a view
+        if (R % per == 0) r = (rr % per) * (R / per) + rr / per;
+    }
+    m.c0 = nc * r / R;
+    m.c1 = nc * (r + 1) / R;
     return m;
 }
 

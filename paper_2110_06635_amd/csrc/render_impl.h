@@ -324,24 +324,25 @@ __device__ __forceinline__ void accum_point(const Cam& c, int L, float fa, bool 
     }
 }
 
-// One view per workgroup: with V views the grid holds V workgroups per
-// point range (view = block % V), so every workgroup's table and wave cache
-// see one view's pixels; the V workgroups of a range are dispatched together
-// and read its points while they are in the caches.
+// One view per workgroup: with V views the grid holds one workgroup per
+// point range and view (view_range_map, views dispatched in groups of
+// kAccumViewGroup), so every workgroup's table and wave cache see one view's
+// pixels, and the workgroups of a range in one group read its points while
+// they are in the caches.
 template <int C, typename S, bool OPTS>
 __global__ void __launch_bounds__(256) k_accum(const float* __restrict__ xs, const float* __restrict__ ys,
                                                const float* __restrict__ zs, const void* __restrict__ feat,
                                                int64_t n, const ViewRec* __restrict__ views, int V, int L,
-                                               float fa, PointOpts o, const uint32_t* __restrict__ keys32,
+                                               int VG, float fa, PointOpts o, const uint32_t* __restrict__ keys32,
                                                float* __restrict__ sums, int32_t* __restrict__ counts) {
     __shared__ AccTable<C> t;
     acc_table_clear<C>(t);
     __syncthreads();
     WaveCache<C> w;
     wcache_init<C>(w);
-    const int view = V > 1 ? (int)(blockIdx.x % (unsigned)V) : 0;
+    int view = 0;
+    RangeMap m = V > 1 ? view_range_map(n, kBlock, V, VG, view) : range_map(n, kBlock);
     const Cam c0 = load_cam(views + view);
-    RangeMap m = V > 1 ? range_map_views(n, kBlock, V) : range_map(n, kBlock);
     // the next chunk's points are loaded while the current one is processed
     float nx = 0.f, ny = 0.f, nz = 0.f, nf[C];
 #pragma unroll
@@ -837,6 +838,8 @@ static inline unsigned persistent_grid(int64_t n, int64_t chunk, int cus, int pe
 constexpr int64_t kAccumRange = 4096;       // accumulation, one view
 constexpr int64_t kAccumViewRange = 2048;   // accumulation, per workgroup of one of several views
 constexpr int64_t kDepthViewRange = 4096;   // depth pass, several views
+// Views per dispatch group of the multi-view accumulation
+constexpr int kAccumViewGroup = 4;
 constexpr int64_t kBackwardRange = 4096;    // backward
 
 // Grid of ranges of `range` points, a multiple of 8 and at least at_least.
@@ -858,17 +861,19 @@ static void forward_points(const FwdArgs& a, hipStream_t st) {
     static const int occ_accum = resident(k_accum<C, S, OPTS>, 0);
     launch_depth(a, st);
     unsigned ga;
+    int vg = a.V;
     if (SINGLE) {
         ga = range_grid(a.n, kAccumRange, persistent_grid(a.n, kBlock, a.cus, occ_accum, 1 << 20));
     } else {
-        // V workgroups (one per view) per point range
+        // R point ranges (a multiple of 8) for each view
         const unsigned per_view = persistent_grid(a.n, kBlock, a.cus, occ_accum, 1 << 20) / (unsigned)a.V;
         int64_t ranges = range_grid(a.n, kAccumViewRange, per_view);
-        ranges = std::min<int64_t>(ranges, (a.n + kBlock - 1) / kBlock);
-        ga = (unsigned)(std::max<int64_t>(ranges, 1) * a.V);
+        ranges = std::max<int64_t>(kXcds, std::min<int64_t>(ranges, (a.n + kBlock - 1) / kBlock) / kXcds * kXcds);
+        ga = (unsigned)(ranges * a.V);
+        vg = std::min(a.V, kAccumViewGroup);
     }
     a.timer.mark(kKAccum, 0, st);
-    k_accum<C, S, OPTS><<<ga, kBlock, 0, st>>>(a.x, a.y, a.z, a.feat, a.n, a.views, a.V, a.L, a.fa, a.opts,
+    k_accum<C, S, OPTS><<<ga, kBlock, 0, st>>>(a.x, a.y, a.z, a.feat, a.n, a.views, a.V, a.L, vg, a.fa, a.opts,
                                                   reinterpret_cast<const uint32_t*>(a.keys), a.sums, a.counts);
     a.timer.mark(kKAccum, 1, st);
 }
