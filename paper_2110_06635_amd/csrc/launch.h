@@ -85,7 +85,6 @@ struct BwdArgs {
 
 hipError_t launch_forward(const FwdArgs& a, hipStream_t st);
 hipError_t launch_backward(const BwdArgs& a, hipStream_t st);
-int backward_points_per_group(int C);
 inline int pack_stride(int C) { return (C + 4 + 3) / 4 * 4; }
 
 struct PrepArgs {

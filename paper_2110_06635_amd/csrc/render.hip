@@ -36,8 +36,6 @@ void launch_reduce(const BwdArgs& a, unsigned groups, hipStream_t st) {
     a.timer.mark(kKReduce, 1, st);
 }
 
-int backward_points_per_group(int C) { return kBlock * (C <= 4 ? ADOP_PPL4 : 2); }
-
 hipError_t launch_forward(const FwdArgs& a, hipStream_t st) {
     if (a.C < 1 || a.C > 16) return hipErrorInvalidValue;
     switch ((a.C - 1) / 4) {
