@@ -145,7 +145,9 @@ def serve_bench(args):
             ("batched", scene16, serve.GpuBackend, dict(max_batch=args.serve_batch, max_inflight=3)),
             ("plain_fp32", scene32, serve.PlainBackend, dict(max_batch=1, max_inflight=1))):
         be = be_cls(ctx, scene, layers=4)
-        srv = serve.Server(be, args.serve_budget_gib << 30, **kw)
+        # each frame is released once its completion is recorded, as a
+        # client consuming the stream would
+        srv = serve.Server(be, args.serve_budget_gib << 30, keep_results=False, **kw)
         # capture every (class, batch size, lane) slot before the trace
         for (w, h) in synth.SERVE_CLASSES:
             cam = synth.serve_camera(np.random.default_rng(1), w, h)
@@ -161,7 +163,7 @@ def serve_bench(args):
         measured = {r.rid for r in reqs}
         srv.completed = [r for r in srv.completed if r.rid in measured]
         results[name] = srv.stats()
-        del srv, be
+        del srv, be, reqs
         torch.cuda.empty_cache()
     b, p = results["batched"], results["plain_fp32"]
     line = {
@@ -193,8 +195,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve", action="store_true", help="run the serving benchmark instead")
     ap.add_argument("--serve-points", type=int, default=50_000_000)
-    ap.add_argument("--serve-requests", type=int, default=2000)
-    ap.add_argument("--serve-warmup", type=int, default=100)
+    ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--serve-warmup", type=int, default=500)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-batch", type=int, default=4)
     ap.add_argument("--serve-budget-gib", type=int, default=96)

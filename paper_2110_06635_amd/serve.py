@@ -12,7 +12,10 @@ One scheduler thread owns the GPU work:
     batch is admitted while others are still on the GPU; a finished batch's
     images are copied to per-request tensors and its graph buffers are
     reused;
-  * a render call that fails fails only the requests of its batch.
+  * a render call that fails fails only the requests of its batch;
+  * with keep_results=False a request's images are released as soon as its
+    completion is recorded (a client that consumes each frame as it
+    arrives), so a long trace does not accumulate output memory.
 Latency is measured from the scheduled arrival to the moment the host sees
 the batch's completion event.
 
@@ -77,8 +80,9 @@ class Backend:
 
 class Server:
     def __init__(self, backend: Backend, mem_budget_bytes: int, max_batch: int = 8,
-                 max_inflight: int = 3, idle_sleep: float = 50e-6):
+                 max_inflight: int = 3, idle_sleep: float = 50e-6, keep_results: bool = True):
         self.backend = backend
+        self.keep_results = keep_results
         self.budget = int(mem_budget_bytes)
         self.max_batch = max_batch
         self.max_inflight = max_inflight
@@ -184,8 +188,9 @@ class Server:
                         outs, err = [None] * len(batch), f"render failed: {e}"
                     now = time.perf_counter()
                     for r, o in zip(batch, outs):
-                        r.result, r.error, r.t_done = o, err, now
+                        r.result, r.error, r.t_done = (o if self.keep_results else None), err, now
                         r.done.set()
+                    outs = None
                     self.backend.release(h)
                     with self._lock:
                         self._inflight.remove(item)
@@ -239,7 +244,9 @@ class Server:
             per_class[f"{k[0]}x{k[1]}"] = {"n": int(lk.size), "p50_ms": float(np.percentile(lk, 50) * 1e3),
                                            "p99_ms": float(np.percentile(lk, 99) * 1e3)}
         span = (max(r.t_done for r in ok) - min(r.arrival for r in ok)) if ok else 0.0
+        errors = collections.Counter(r.error for r in self.completed if r.error is not None)
         return {"completed": len(ok), "failed": len(self.completed) - len(ok), "rejected": self.rejected,
+                "errors": dict(errors.most_common(3)),
                 "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
                 "mean_ms": float(lat.mean() * 1e3), "renders_per_s": len(ok) / span if span > 0 else 0.0,
                 "batches": self.batches,

@@ -111,6 +111,7 @@ def test_failure_isolated_to_its_batch():
     srv.stop()
     bad = [r for r in reqs if r.error]
     assert bad and all(r.batch_id == 3 for r in bad)
+    assert srv.stats()["errors"] == {"render failed: injected failure": len(bad)}
     good = [r for r in reqs if not r.error]
     assert len(good) + len(bad) == 120 and len(good) > 100
     assert all(r.result is not None for r in good)
@@ -136,3 +137,16 @@ def test_unbatched_baseline_is_fifo():
     order = [h["cams"][0] for h in fb.launches]
     assert order == [r.camera for r in sorted(reqs, key=lambda r: r.rid)]
     assert fb.max_live == 1
+
+
+def test_results_released_when_not_kept():
+    """keep_results=False: completions and latencies are recorded, the
+    images are not held by the requests."""
+    fb = FakeBackend(per_view_s=0.001, fixed_s=0.0005)
+    srv = serve.Server(fb, 10 ** 10, max_batch=4, max_inflight=2, keep_results=False)
+    srv.start()
+    reqs = serve.replay(srv, trace(100))
+    srv.stop()
+    st = srv.stats()
+    assert st["completed"] == 100 and st["failed"] == 0 and st["errors"] == {}
+    assert all(r.result is None and r.error is None and r.latency > 0 for r in reqs)
