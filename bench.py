@@ -205,6 +205,8 @@ def main():
     ap.add_argument("--cull", default="", choices=["", "backface", "printed"],
                     help="normal culling with seeded random unit normals")
     ap.add_argument("--log-features", action="store_true", help="features are logarithmic descriptors")
+    ap.add_argument("--no-visibility", action="store_true",
+                    help="the forward records no blend-set bits; the backward re-tests every point")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -251,7 +253,7 @@ def main():
     flags = ((adop.FLAG_DISCARD if args.discard else 0) | (adop.FLAG_LOG_FEATURES if args.log_features else 0) |
              {"": 0, "backface": adop.FLAG_CULL_BACKFACE, "printed": adop.FLAG_CULL_PRINTED}[args.cull])
     options = [o for o, on in (("discard", args.discard), ("log_features", args.log_features),
-                               (f"cull_{args.cull}", bool(args.cull))) if on]
+                               (f"cull_{args.cull}", bool(args.cull)), ("no_visibility", args.no_visibility)) if on]
 
     def run(dtype, steps, warmup, timing):
         code = adop.DTYPES[dtype]
@@ -276,7 +278,9 @@ def main():
             pre["knn_radius_s"] = round(time.perf_counter() - t0, 3)
         frame = adop.Frame(s.cams, s.layers, C, dev)
         ws = ctx.workspace(C, V, frame.pixels)
-        adop.render_forward(ctx, scene, frame.cams, s.layers, alpha=s.alpha, frame=frame, workspace=ws, flags=flags)
+        rec = not args.no_visibility
+        adop.render_forward(ctx, scene, frame.cams, s.layers, alpha=s.alpha, frame=frame, workspace=ws, flags=flags,
+                            record_visibility=rec)
         G = l1_grad(frame, target)
         out = (torch.empty((scene.n, C), dtype=torch.float32, device=dev),
                torch.empty((3, scene.n), dtype=torch.float32, device=dev),
@@ -285,7 +289,7 @@ def main():
 
         def step():
             adop.render_forward(ctx, scene, frame.cams, s.layers, alpha=s.alpha, frame=frame, workspace=ws,
-                                flags=flags)
+                                flags=flags, record_visibility=rec)
             adop.render_backward(ctx, scene, frame, G, alpha=s.alpha, out=out, workspace=ws, flags=flags)
 
         for _ in range(warmup):

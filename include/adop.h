@@ -139,6 +139,13 @@ typedef struct adop_frame {
     uint64_t* keys;            /* [pixels] (bits(z) << 32 | orig_index), empty = ~0 */
     int32_t* counts;           /* [pixels] number of blended points |Lambda| */
     int64_t pixels;            /* must equal the total of adop_views_layout */
+    uint8_t* visible;          /* optional, [V][n]: the forward sets bit l of visible[v * n + i]
+                                  when point i is in the blend set of layer l of view v (Eq.
+                                  depthtest, after culling and discarding), and clears the other
+                                  bits; the backward of the same frame then reads the bits
+                                  instead of testing every point against the pixel records, and
+                                  skips points without any.  NULL: not written; the backward
+                                  re-renders every point. */
 } adop_frame;
 
 typedef struct adop_context adop_context;
@@ -226,7 +233,8 @@ adop_status adop_render_forward(adop_context* ctx, const adop_scene* scene,
 
 /* Backward pass (Eqs. partial, induce, gradp, spatialderiv, tangent).
  * Inputs: the frame written by adop_render_forward with the same scene,
- * cameras and params, and grad_images = dL/dI in the image layout.  Outputs
+ * cameras and params (including frame->visible when it is set), and
+ * grad_images = dL/dI in the image layout.  Outputs
  * (device, overwritten):
  *   dfeat [n][C] FP32   -- derivative of Eq. blend (points in the blend set)
  *   dpos  [3][n] FP32   -- dL/dx, dL/dy, dL/dz from the approximate spatial

@@ -59,7 +59,7 @@ class SceneDesc(ct.Structure):
 
 class FrameDesc(ct.Structure):
     _fields_ = [("images", ct.c_void_p), ("keys", ct.c_void_p), ("counts", ct.c_void_p),
-                ("pixels", ct.c_int64)]
+                ("pixels", ct.c_int64), ("visible", ct.c_void_p)]
 
 
 _LIB = None
@@ -328,9 +328,13 @@ class Frame:
         self.images = torch.empty(channels * self.pixels, dtype=torch.float32, device=device)
         self.keys = torch.empty(self.pixels, dtype=torch.int64, device=device)
         self.counts = torch.empty(self.pixels, dtype=torch.int32, device=device)
+        # [V, n] blend-set bits per point and view, written by a forward that
+        # records them and read by the backward of the same frame
+        self.visible: Optional[torch.Tensor] = None
 
     def desc(self) -> FrameDesc:
-        return FrameDesc(_ptr(self.images), _ptr(self.keys), _ptr(self.counts), self.pixels)
+        return FrameDesc(_ptr(self.images), _ptr(self.keys), _ptr(self.counts), self.pixels,
+                         _ptr(self.visible) if self.visible is not None else None)
 
     def layer_image(self, v: int, l: int) -> torch.Tensor:
         cam = self.cams[v]
@@ -353,7 +357,11 @@ class Frame:
 
 def render_forward(ctx: Context, scene: Scene, cams, layers: int, alpha: float = 0.01, flags: int = 0,
                    background=None, frame: Optional[Frame] = None, stream=None,
-                   workspace: Optional[torch.Tensor] = None, gamma: float = GAMMA) -> Frame:
+                   workspace: Optional[torch.Tensor] = None, gamma: float = GAMMA,
+                   record_visibility: bool = True) -> Frame:
+    """record_visibility: also write frame.visible ([V, n] uint8, bit l =
+    the point is in layer l's blend set), which lets render_backward skip
+    the points that blend nowhere; False leaves frame.visible unset."""
     C = scene.channels
     if frame is None:
         frame = Frame(cams, layers, C, scene.x.device)
@@ -365,6 +373,12 @@ def render_forward(ctx: Context, scene: Scene, cams, layers: int, alpha: float =
             raise ValueError("cameras, layers or channels do not match the given frame")
         frame.cams = arr
     ws = workspace if workspace is not None else ctx.workspace(C, len(frame.cams), frame.pixels)
+    if record_visibility:
+        shape = (len(frame.cams), scene.n)
+        if frame.visible is None or tuple(frame.visible.shape) != shape or frame.visible.device != scene.x.device:
+            frame.visible = torch.empty(shape, dtype=torch.uint8, device=scene.x.device)
+    else:
+        frame.visible = None
     p, keep = _params(layers, alpha, flags, background, C, gamma)
     sd = scene.desc()
     fd = frame.desc()
@@ -389,6 +403,8 @@ def render_backward(ctx: Context, scene: Scene, frame: Frame, grad: torch.Tensor
                torch.empty((V, 6), dtype=torch.float64, device=dev),
                torch.empty((V, 9), dtype=torch.float64, device=dev))
     dfeat, dpos, dpose, dintr = out
+    if frame.visible is not None and tuple(frame.visible.shape) != (V, scene.n):
+        raise ValueError("frame.visible was recorded for another scene")
     ws = workspace if workspace is not None else ctx.workspace(C, V, frame.pixels)
     p, keep = _params(frame.layers, alpha, flags, background, C, gamma)
     sd = scene.desc()

@@ -292,6 +292,7 @@ adop::FwdArgs fwd_args(adop_context* ctx, const adop_scene* scene, const adop_ca
     a.background = params->background;
     a.opts = point_opts(scene, params);
     a.timer = timer_of(ctx);
+    a.vis = frame->visible;
     return a;
 }
 
@@ -514,6 +515,7 @@ adop_status adop_render_backward(adop_context* ctx, const adop_scene* scene, con
     a.background = params->background;
     a.opts = point_opts(scene, params);
     a.timer = timer_of(ctx);
+    a.vis = frame->visible;
     hipError_t e = adop::launch_backward(a, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "backward launch");
     return ADOP_OK;

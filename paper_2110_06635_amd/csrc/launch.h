@@ -49,6 +49,7 @@ struct FwdArgs {
     float* images;
     const float* background;   // host [C] or null
     PointOpts opts;
+    uint8_t* vis = nullptr;   // optional [V][n] blend-set bits per point and view
     Timer timer;
 };
 
@@ -80,6 +81,7 @@ struct BwdArgs {
     double* dpose;
     double* dintr;
     const float* background;
+    const uint8_t* vis = nullptr;   // optional [V][n], written by the forward
     Timer timer;
 };
 

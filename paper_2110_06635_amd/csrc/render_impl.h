@@ -284,8 +284,9 @@ __device__ __forceinline__ void acc_table_flush(AccTable<C>& t, float* __restric
     }
 }
 
+// Returns the blend-set bits of the point (bit l: it passed at layer l).
 template <int C, bool OPTS>
-__device__ __forceinline__ void accum_point(const Cam& c, int L, float fa, bool live, float x, float y, float z,
+__device__ __forceinline__ uint32_t accum_point(const Cam& c, int L, float fa, bool live, float x, float y, float z,
                                             const float (&f)[C], const PointOpts& o, const PointExtra& e,
                                             const uint32_t* __restrict__ keys32, AccTable<C>& t,
                                             float* __restrict__ sums, int32_t* __restrict__ counts, WaveCache<C>& w) {
@@ -312,12 +313,15 @@ __device__ __forceinline__ void accum_point(const Cam& c, int L, float fa, bool 
             mz[l] = __uint_as_float(keys32[2 * (uint64_t)pix[l] + 1]);   // pix is valid for every lane
         }
     }
+    uint32_t seen = 0;
 #pragma unroll
     for (int l = 0; l < kMaxLayers; ++l) {
         if (l >= L) break;
         bool pass = in[l] && p.Z <= __fmul_rn(mz[l], fa);
+        seen |= (uint32_t)pass << l;
         accum_update<C>(pass, pix[l], f, t, sums, counts, w);
     }
+    return seen;
 }
 
 // One view per workgroup: with V views the grid holds one workgroup per
@@ -330,7 +334,8 @@ __global__ void __launch_bounds__(256) k_accum(const float* __restrict__ xs, con
                                                const float* __restrict__ zs, const void* __restrict__ feat,
                                                int64_t n, const ViewRec* __restrict__ views, int V, int L,
                                                int VG, float fa, PointOpts o, const uint32_t* __restrict__ keys32,
-                                               float* __restrict__ sums, int32_t* __restrict__ counts) {
+                                               float* __restrict__ sums, int32_t* __restrict__ counts,
+                                               uint8_t* __restrict__ vis) {
     __shared__ AccTable<C> t;
     acc_table_clear<C>(t);
     __syncthreads();
@@ -369,7 +374,8 @@ __global__ void __launch_bounds__(256) k_accum(const float* __restrict__ xs, con
 #pragma unroll
             for (int ch = 0; ch < C; ++ch) f[ch] = expf(f[ch]);
         }
-        accum_point<C, OPTS>(c0, L, fa, live, x, y, z, f, o, e, keys32, t, sums, counts, w);
+        const uint32_t seen = accum_point<C, OPTS>(c0, L, fa, live, x, y, z, f, o, e, keys32, t, sums, counts, w);
+        if (vis != nullptr && live) vis[(uint64_t)view * (uint64_t)n + (uint64_t)(c * kBlock + threadIdx.x)] = (uint8_t)seen;
     }
     wcache_flush<C>(w, t, sums, counts);
     __syncthreads();
@@ -517,24 +523,31 @@ __device__ __forceinline__ void layer_work(const float* __restrict__ pack, uint3
 // through the projection; adds the 15 pose/intrinsics terms to acc (FP32).
 // The layer loop is not unrolled (it keeps the kernel within the instruction
 // cache); w_l = w >> l, h_l = h >> l and layer bases follow one another.
+// `known`: the point's blend-set bits as the forward recorded them, or
+// kVisUnknown to test the point against the records here.
+constexpr uint32_t kVisUnknown = 0xffffffffu;
+
 template <int C, bool OPTS>
 __device__ __forceinline__ void point_view(const Cam& c, int L, float fa, bool spatial_all,
                                            const float* __restrict__ pack, bool live, float x, float y, float z,
                                            const float (&tau)[C], float (&dt)[C], float (&dp)[3], float (&acc)[15],
-                                           bool& any, const PointOpts& o, const PointExtra& e) {
+                                           bool& any, const PointOpts& o, const PointExtra& e, uint32_t known) {
     using PL = PackLayout<C>;
+    if (known == 0) return;   // in no blend set: no gradient (known only without SPATIAL_ALL)
     Proj p = project(c, x, y, z);
     if (!(live && p.ok)) return;
-    uint32_t lmask = 0xffu;
-    if (OPTS && (o.flags & (kOptCullBack | kOptCullPrinted | kOptDiscard))) {
-        if (!normal_kept(o, c, p, e)) return;
-        lmask = discard_mask(o, c, p, e, L);
-    }
     float gu = 0.f, gv = 0.f;
     // bit l of work: the layer needs the neighbour records; bit l of seen:
     // the point is in the layer's blend set
-    uint32_t work = 0, seen = 0;
-    {
+    uint32_t work = known, seen = known;
+    if (known == kVisUnknown) {
+        uint32_t lmask = 0xffu;
+        if (OPTS && (o.flags & (kOptCullBack | kOptCullPrinted | kOptDiscard))) {
+            if (!normal_kept(o, c, p, e)) return;
+            lmask = discard_mask(o, c, p, e, L);
+        }
+        work = 0;
+        seen = 0;
         float mz[kMaxLayers];
         bool in[kMaxLayers];
 #pragma unroll
@@ -627,7 +640,7 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
                                                   float fa, uint32_t flags, PointOpts o,
                                                   const float* __restrict__ pack,
                                                   float* __restrict__ dfeat, float* __restrict__ dpos,
-                                                  double* __restrict__ partials) {
+                                                  double* __restrict__ partials, const uint8_t* __restrict__ vis) {
     // single view: [256 lanes][16] FP64 per-lane sums; several views:
     // [4 waves][V][16] per-wave sums
     extern __shared__ double acc_lds[];
@@ -637,6 +650,9 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
     for (int j = threadIdx.x; j < slots; j += blockDim.x) acc_lds[j] = 0.0;
     __syncthreads();
     const bool spatial_all = (flags & 1u) != 0;
+    // the forward's blend-set bits replace the tests (not with SPATIAL_ALL,
+    // which needs every in-bounds point)
+    const bool use_vis = vis != nullptr && !spatial_all;
     const Cam c0 = load_cam(views);
     float acc1[15];
 #pragma unroll
@@ -650,10 +666,12 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
         float tau[PPL][C], dt[PPL][C], dp[PPL][3];
         bool live[PPL];
         PointExtra ex[PPL];
+        uint32_t known[PPL];
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
             int64_t i = wbase + (int64_t)k * kWave + lane;
             live[k] = i < n;
+            known[k] = (SINGLE && use_vis && live[k]) ? (uint32_t)vis[i] : kVisUnknown;
             px_[k] = py_[k] = pz_[k] = 0.f;
 #pragma unroll
             for (int ch = 0; ch < C; ++ch) { tau[k][ch] = 0.f; dt[k][ch] = 0.f; }
@@ -675,7 +693,7 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
 #pragma unroll
             for (int k = 0; k < PPL; ++k)
                 point_view<C, OPTS>(c0, L, fa, spatial_all, pack, live[k], px_[k], py_[k], pz_[k], tau[k], dt[k], dp[k],
-                              acc1, any, o, ex[k]);
+                              acc1, any, o, ex[k], known[k]);
             if (++since == kSuper || c + 1 == m.c1) {
                 double* slot = acc_lds + threadIdx.x * 16;
 #pragma unroll
@@ -693,9 +711,13 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
                 for (int t = 0; t < 15; ++t) acc[t] = 0.f;
                 bool any = false;
 #pragma unroll
-                for (int k = 0; k < PPL; ++k)
+                for (int k = 0; k < PPL; ++k) {
+                    const int64_t i = wbase + (int64_t)k * kWave + lane;
+                    const uint32_t kn = (use_vis && live[k]) ? (uint32_t)vis[(uint64_t)v * (uint64_t)n + (uint64_t)i]
+                                                             : kVisUnknown;
                     point_view<C, OPTS>(cv, L, fa, spatial_all, pack, live[k], px_[k], py_[k], pz_[k], tau[k], dt[k],
-                                  dp[k], acc, any, o, ex[k]);
+                                  dp[k], acc, any, o, ex[k], kn);
+                }
                 reduce_terms(acc, any, acc_lds + (wave * V + v) * 16, lane);
             }
         }
@@ -872,7 +894,8 @@ static void forward_points(const FwdArgs& a, hipStream_t st) {
     }
     a.timer.mark(kKAccum, 0, st);
     k_accum<C, S, OPTS><<<ga, kBlock, 0, st>>>(a.x, a.y, a.z, a.feat, a.n, a.views, a.V, a.L, vg, a.fa, a.opts,
-                                                  reinterpret_cast<const uint32_t*>(a.keys), a.sums, a.counts);
+                                                  reinterpret_cast<const uint32_t*>(a.keys), a.sums, a.counts,
+                                                  a.vis);
     a.timer.mark(kKAccum, 1, st);
 }
 
@@ -901,7 +924,8 @@ static unsigned backward_points(const BwdArgs& a, hipStream_t st) {
     g = std::min<unsigned>(range_grid(a.n, kBackwardRange, g), (unsigned)a.groups / kXcds * kXcds);
     a.timer.mark(kKBackward, 0, st);
     k_backward<C, S, PPL, SINGLE, OPTS><<<g, kBlock, lds, st>>>(a.x, a.y, a.z, a.feat, a.n, a.views, a.V, a.L, a.fa,
-                                                          a.flags, a.opts, a.pack, a.dfeat, a.dpos, a.partials);
+                                                          a.flags, a.opts, a.pack, a.dfeat, a.dpos, a.partials,
+                                                          a.vis);
     a.timer.mark(kKBackward, 1, st);
     return g;
 }

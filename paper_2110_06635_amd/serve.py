@@ -334,7 +334,7 @@ class GpuBackend(Backend):
         else:
             fr, ws = slot
             frame = self.adop.render_forward(self.ctx, self.scene, cams, self.layers, alpha=self.alpha,
-                                             frame=fr, workspace=ws, stream=st)
+                                             frame=fr, workspace=ws, stream=st, record_visibility=False)
         with torch.cuda.stream(st):
             outs = [frame.images[self.C * int(frame.offsets[v, 0]):
                                  self.C * (int(frame.offsets[v, 0]) + self._pixels(klass))].clone()

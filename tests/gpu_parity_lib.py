@@ -87,11 +87,29 @@ def compare_backward(scene, got, ref, tol_feat=1e-5, tol_pos=1e-4, tol_cam=1e-5)
     return report
 
 
+def check_visibility(fr, s):
+    """The forward's blend-set bits against the bit-exact counts: for every
+    view and layer, the number of points with bit l set equals the sum of
+    the layer's counts, and no bit at or above L is set."""
+    vis = fr.visible.cpu().numpy()
+    counts = fr.counts.cpu().numpy()
+    for v, cam in enumerate(s.cams):
+        assert not np.any(vis[v] >> s.layers), "bits above the layer count"
+        for l in range(s.layers):
+            o = int(fr.offsets[v, l])
+            npx = (cam.width >> l) * (cam.height >> l)
+            got = int(np.count_nonzero((vis[v] >> l) & 1))
+            want = int(counts[o:o + npx].sum(dtype=np.int64))
+            assert got == want, f"view {v} layer {l}: {got} points flagged, counts sum to {want}"
+    return True
+
+
 def run_case(A, ctx, O, s, dtype="f32", prepare=True, flags=0, grad_seed=99, backward=True, alpha=None,
-             normals=None, radius=None, beta=None, gamma=1.5):
+             normals=None, radius=None, beta=None, gamma=1.5, visibility=True):
     """Forward (+ backward) on GPU and oracle; returns reports.  normals
     [n,3], radius [n] and beta [n] (caller's order) go with the culling and
-    discarding flags."""
+    discarding flags.  visibility: the forward records the blend-set bits
+    and the backward reads them (False: the backward re-tests every point)."""
     import torch
     alpha = s.alpha if alpha is None else alpha
     scene, widened = to_device_scene(A, ctx, s, dtype, prepare)
@@ -101,11 +119,14 @@ def run_case(A, ctx, O, s, dtype="f32", prepare=True, flags=0, grad_seed=99, bac
         scene.set_discard(ctx, torch.from_numpy(np.ascontiguousarray(beta, np.float32)).cuda(),
                           torch.from_numpy(np.ascontiguousarray(radius, np.float32)).cuda())
     opt = dict(flags=flags, normals=normals, radius=radius, beta=beta, gamma=gamma)
-    fr = A.render_forward(ctx, scene, s.cams, s.layers, alpha=alpha, flags=flags, background=s.bg(), gamma=gamma)
+    fr = A.render_forward(ctx, scene, s.cams, s.layers, alpha=alpha, flags=flags, background=s.bg(), gamma=gamma,
+                          record_visibility=visibility)
     torch.cuda.synchronize()
     ref = O.forward(s.pos, widened, s.cams, s.layers, alpha=alpha, background=s.bg(), want64=True, **opt)
     scale = max(1.0, float(np.max(np.abs(widened))) if widened.size else 1.0)
     rep = {"image_rel": compare_forward(fr, ref, scale=scale)}
+    if visibility and s.n > 0:
+        rep["visible_bits"] = check_visibility(fr, s)
     if backward:
         total = fr.pixels
         G = synth.upstream_grad(total * s.c, grad_seed)

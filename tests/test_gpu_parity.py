@@ -34,11 +34,14 @@ def small_scene(seed, n, w=160, h=120, L=3, c=4, dist=True, box=2.0, depth=6.0):
     return synth.Scene(pos, feat, [cam], layers=L, name=f"small-{seed}")
 
 
-def test_small_forward_backward(G):
+@pytest.mark.parametrize("visibility", [True, False])
+def test_small_forward_backward(G, visibility):
+    """With the forward's blend-set bits read by the backward, and with the
+    backward re-testing every point."""
     A, ctx, O = G
     s = small_scene(1, 20000)
-    say("small 20k 160x120 L3 f32 prepared")
-    rep = run_case(A, ctx, O, s)
+    say(f"small 20k 160x120 L3 f32 prepared, recorded visibility {visibility}")
+    rep = run_case(A, ctx, O, s, visibility=visibility)
     print(rep)
 
 
