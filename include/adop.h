@@ -144,7 +144,8 @@ typedef struct adop_frame {
                                   depthtest, after culling and discarding), and clears the other
                                   bits; the backward of the same frame then reads the bits
                                   instead of testing every point against the pixel records, and
-                                  skips points without any.  NULL: not written; the backward
+                                  skips points without any (not with ADOP_FLAG_SPATIAL_ALL, which
+                                  needs every in-bounds point).  NULL: not written; the backward
                                   re-renders every point. */
 } adop_frame;
 
