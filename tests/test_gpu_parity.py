@@ -218,3 +218,35 @@ def test_config2_forward_backward(G):
     say("config 2 (10M planes, 1080p, L5) forward+backward")
     rep = run_case(A, ctx, O, s)
     print(rep)
+
+
+@pytest.mark.parametrize("case", ["single", "multiview", "cull_discard"])
+def test_recorded_bits_equal_retest(G, case):
+    """The backward that reads the forward's blend-set bits and the backward
+    that re-tests every point make the same decisions and the same FP32/FP64
+    operations in the same order: their outputs are bit-identical."""
+    import torch
+    A, ctx, O = G
+    flags = 0
+    if case == "multiview":
+        s = synth.Scene(*synth.gaussian_mixture(60000, 8, 1.5, 0.3, 4, 47),
+                        synth.orbit_cameras(5, 6.0, 48, width=128, height=96, f=110.0), layers=4, name="mv-bits")
+    else:
+        s = synth.config2(n_planes=20, per_plane=15000)
+    scene, _ = to_device_scene(A, ctx, s)
+    if case == "cull_discard":
+        pos, _, nrm = synth.planes(20, 15000, 4, 1002, with_normals=True)
+        assert np.array_equal(pos, s.pos)
+        scene.set_normals(ctx, torch.from_numpy(np.ascontiguousarray(nrm)).cuda())
+        scene.set_discard(ctx, torch.from_numpy(synth.uniform01(s.n, 49)).cuda())   # GPU 4-NN radius
+        flags = A.FLAG_CULL_BACKFACE | A.FLAG_DISCARD
+    say(f"recorded bits vs re-test: {case}, {s.n} points, {len(s.cams)} views")
+    fr = A.render_forward(ctx, scene, s.cams, s.layers, flags=flags, background=s.bg())
+    assert fr.visible is not None
+    G_ = torch.from_numpy(synth.upstream_grad(fr.pixels * s.c, 5)).cuda()
+    with_bits = [t.cpu().numpy() for t in A.render_backward(ctx, scene, fr, G_, flags=flags, background=s.bg())]
+    fr.visible = None
+    retest = [t.cpu().numpy() for t in A.render_backward(ctx, scene, fr, G_, flags=flags, background=s.bg())]
+    for name, a, b in zip(("dfeat", "dpos", "dpose", "dintr"), with_bits, retest):
+        assert np.array_equal(a, b), f"{name} differs"
+    assert np.count_nonzero(with_bits[0]) > 0
