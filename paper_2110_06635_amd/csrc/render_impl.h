@@ -660,6 +660,18 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
     int since = 0;
 
     RangeMap m = range_map(n, (int64_t)kBlock * PPL);
+    // single view: the blend-set bits of the next chunk are loaded one chunk
+    // ahead, so a point that blends nowhere needs neither its position nor
+    // its features and its loads are not issued
+    uint32_t known_next[PPL];
+    auto fetch_known = [&](int64_t cc) {
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+            const int64_t i = cc * kBlock * PPL + (int64_t)wave * kWave * PPL + (int64_t)k * kWave + lane;
+            known_next[k] = (SINGLE && use_vis && i < n) ? (uint32_t)vis[i] : kVisUnknown;
+        }
+    };
+    if (m.c0 < m.c1) fetch_known(m.c0);
     for (int64_t c = m.c0; c < m.c1; ++c) {
         const int64_t wbase = c * kBlock * PPL + (int64_t)wave * kWave * PPL;
         float px_[PPL], py_[PPL], pz_[PPL];
@@ -668,15 +680,17 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
         PointExtra ex[PPL];
         uint32_t known[PPL];
 #pragma unroll
+        for (int k = 0; k < PPL; ++k) known[k] = known_next[k];
+        if (c + 1 < m.c1) fetch_known(c + 1);
+#pragma unroll
         for (int k = 0; k < PPL; ++k) {
             int64_t i = wbase + (int64_t)k * kWave + lane;
             live[k] = i < n;
-            known[k] = (SINGLE && use_vis && live[k]) ? (uint32_t)vis[i] : kVisUnknown;
             px_[k] = py_[k] = pz_[k] = 0.f;
 #pragma unroll
             for (int ch = 0; ch < C; ++ch) { tau[k][ch] = 0.f; dt[k][ch] = 0.f; }
             dp[k][0] = dp[k][1] = dp[k][2] = 0.f;
-            if (live[k]) {
+            if (live[k] && known[k] != 0) {
                 px_[k] = ld_nt(xs + i);
                 py_[k] = ld_nt(ys + i);
                 pz_[k] = ld_nt(zs + i);
