@@ -873,8 +873,9 @@ constexpr int64_t kDepthViewRange = 4096;   // depth pass, several views
 // Views per dispatch group of the multi-view accumulation
 constexpr int kAccumViewGroup = 4;
 constexpr int64_t kBackwardRange = 4096;    // backward
-// Points per lane and chunk of the backward (their loads are issued together)
-constexpr int kBwdPointsPerLane = 2;
+// Points per lane and chunk of the backward (their loads are issued
+// together): four up to 4 channels, two above (registers)
+template <int C> constexpr int bwd_points_per_lane() { return C <= 4 ? 4 : 2; }
 
 // Grid of ranges of `range` points, a multiple of 8 and at least at_least.
 static inline unsigned range_grid(int64_t n, int64_t range, unsigned at_least) {
@@ -930,7 +931,7 @@ static hipError_t forward_impl(const FwdArgs& a, hipStream_t st) {
 
 template <int C, typename S, bool SINGLE, bool OPTS>
 static unsigned backward_points(const BwdArgs& a, hipStream_t st) {
-    constexpr int PPL = kBwdPointsPerLane;
+    constexpr int PPL = bwd_points_per_lane<C>();
     const size_t lds = SINGLE ? (size_t)kBlock * 16 * sizeof(double) : (size_t)4 * a.V * 16 * sizeof(double);
     static const int occ = resident(k_backward<C, S, PPL, SINGLE, OPTS>,
                                     SINGLE ? lds : (size_t)4 * kMaxViewsBwd * 16 * sizeof(double));
