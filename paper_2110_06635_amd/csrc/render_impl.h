@@ -29,6 +29,7 @@
 // wave sum (one pixel) into a per-wave register cache of pixel sums, or with
 // segmented sums over runs, in front of a workgroup table in LDS and the
 // global atomics.
+#include <type_traits>
 #include "device.h"
 #include "launch.h"
 
@@ -874,8 +875,11 @@ constexpr int64_t kDepthViewRange = 4096;   // depth pass, several views
 constexpr int kAccumViewGroup = 4;
 constexpr int64_t kBackwardRange = 4096;    // backward
 // Points per lane and chunk of the backward (their loads are issued
-// together): four up to 4 channels, two above (registers)
-template <int C> constexpr int bwd_points_per_lane() { return C <= 4 ? 4 : 2; }
+// together): four for FP32 features up to 4 channels, two otherwise
+// (registers; the 16-bit types convert on load)
+template <int C, typename S> constexpr int bwd_points_per_lane() {
+    return (C <= 4 && std::is_same<S, F32>::value) ? 4 : 2;
+}
 
 // Grid of ranges of `range` points, a multiple of 8 and at least at_least.
 static inline unsigned range_grid(int64_t n, int64_t range, unsigned at_least) {
@@ -931,7 +935,7 @@ static hipError_t forward_impl(const FwdArgs& a, hipStream_t st) {
 
 template <int C, typename S, bool SINGLE, bool OPTS>
 static unsigned backward_points(const BwdArgs& a, hipStream_t st) {
-    constexpr int PPL = bwd_points_per_lane<C>();
+    constexpr int PPL = bwd_points_per_lane<C, S>();
     const size_t lds = SINGLE ? (size_t)kBlock * 16 * sizeof(double) : (size_t)4 * a.V * 16 * sizeof(double);
     static const int occ = resident(k_backward<C, S, PPL, SINGLE, OPTS>,
                                     SINGLE ? lds : (size_t)4 * kMaxViewsBwd * 16 * sizeof(double));
