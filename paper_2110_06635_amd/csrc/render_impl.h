@@ -8,12 +8,14 @@
 //   k_depth      project every point into every view and layer, 64-bit
 //                atomic minimum of (depth bits << 32 | original index)
 //   k_accum      fuzzy depth test z <= (1+alpha) min_z (Eq. depthtest),
-//                FP32 sums of the features and an integer count
+//                FP32 sums of the features and an integer count; optionally
+//                each point's blend-set bits (one byte per point and view)
 //   k_normalize  mean of the blend set or the background (Eq. blend)
 // Backward:
 //   k_pack       per-pixel record {G, <G,I>, min_z, (1+alpha) min_z, n}
-//   k_backward   re-render every point (the blend sets are not stored),
-//                feature gradient, approximate spatial gradient (Eqs. induce,
+//   k_backward   re-render every point (the blend sets are not stored), or
+//                take the forward's blend-set bits and skip the points
+//                without any; feature gradient, approximate spatial gradient (Eqs. induce,
 //                gradp, spatialderiv), chain to positions, pose (Eq. tangent)
 //                and intrinsics; per-point terms in FP32, pose/intrinsics
 //                sums in FP64 with a fixed reduction order
