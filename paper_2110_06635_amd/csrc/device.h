@@ -510,35 +510,14 @@ __device__ __forceinline__ RangeMap view_range_map(int64_t n, int64_t chunk, int
 // workgroup-private open-addressing tables in LDS (pixel -> partial result)
 // ----------------------------------------------------------------------------
 constexpr uint32_t kEmptySlot = 0xffffffffu;
-constexpr int kProbes = 8;
 
 template <int BITS>
 __device__ __forceinline__ uint32_t hash_slot(uint32_t pix) {
     return (pix * 2654435761u) >> (32 - BITS);
 }
 
-// Find or claim the slot of `pix`; -1 (and *full = 1) when kProbes slots
-// after its home slot are taken by other pixels.
-template <int BITS>
-__device__ __forceinline__ int table_slot(uint32_t* tkey, uint32_t pix, int* full) {
-    constexpr uint32_t mask = (1u << BITS) - 1;
-    uint32_t h = hash_slot<BITS>(pix);
-#pragma unroll 1
-    for (int p = 0; p < kProbes; ++p) {
-        uint32_t k = __hip_atomic_load(&tkey[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (k == pix) return (int)h;
-        if (k == kEmptySlot) {
-            uint32_t old = atomicCAS(&tkey[h], kEmptySlot, pix);
-            if (old == kEmptySlot || old == pix) return (int)h;
-        }
-        h = (h + 1) & mask;
-    }
-    *full = 1;
-    return -1;
-}
-
-// Direct-mapped variant with two fixed probes (home slot and its neighbour):
-// no loop; -1 when both are taken by other pixels.
+// Find or claim the slot of `pix` with two fixed probes (home slot and its
+// neighbour): no loop; -1 when both are taken by other pixels.
 template <int BITS>
 __device__ __forceinline__ int table_slot2(uint32_t* tkey, uint32_t pix) {
     constexpr uint32_t mask = (1u << BITS) - 1;
