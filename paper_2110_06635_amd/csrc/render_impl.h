@@ -161,14 +161,26 @@ template <int C> struct AccTable {
     int32_t cnt[H];
 };
 
+// The global per-pixel FP32 sums of the accumulation, planar [C][pixels]:
+// the C + 1 atomics of one update go to different cache lines (and L2
+// channels) instead of queueing on one line, which matters where few points
+// blend per pixel and most updates reach the global sums.
+struct SumsRef {
+    float* p;
+    int64_t P;   // pixels
+};
 template <int C>
-__device__ __forceinline__ void table_add(AccTable<C>& t, float* __restrict__ sums, int32_t* __restrict__ counts,
+__device__ __forceinline__ float* sum_at(const SumsRef& s, uint64_t pix, int c) {
+    return s.p + (uint64_t)c * (uint64_t)s.P + pix;
+}
+
+template <int C>
+__device__ __forceinline__ void table_add(AccTable<C>& t, const SumsRef& sums, int32_t* __restrict__ counts,
                                           uint32_t pix, const float (&s)[C], int32_t k) {
     int slot = table_slot2<AccTable<C>::bits>(t.key, pix);
     if (slot < 0) {
-        float* dst = sums + (uint64_t)pix * C;
 #pragma unroll
-        for (int c = 0; c < C; ++c) atomic_add_f32(dst + c, s[c]);
+        for (int c = 0; c < C; ++c) atomic_add_f32(sum_at<C>(sums, pix, c), s[c]);
         atomic_add_i32(counts + pix, k);
         return;
     }
@@ -200,7 +212,7 @@ __device__ __forceinline__ void wcache_init(WaveCache<C>& w) {
 // s and k are wave-uniform; every lane calls this.
 template <int C>
 __device__ __forceinline__ void wcache_add(WaveCache<C>& w, uint32_t p0, const float (&s)[C], int32_t k,
-                                           AccTable<C>& t, float* __restrict__ sums, int32_t* __restrict__ counts) {
+                                           AccTable<C>& t, const SumsRef& sums, int32_t* __restrict__ counts) {
     const int slot = (int)((p0 * 2654435761u) >> 26);
     const uint32_t ck = (uint32_t)__builtin_amdgcn_readlane((int)w.key, slot);
     const bool me = lane_id() == slot;
@@ -220,7 +232,7 @@ __device__ __forceinline__ void wcache_add(WaveCache<C>& w, uint32_t p0, const f
 }
 
 template <int C>
-__device__ __forceinline__ void wcache_flush(WaveCache<C>& w, AccTable<C>& t, float* __restrict__ sums,
+__device__ __forceinline__ void wcache_flush(WaveCache<C>& w, AccTable<C>& t, const SumsRef& sums,
                                              int32_t* __restrict__ counts) {
     if (w.key != kEmptySlot) table_add<C>(t, sums, counts, w.key, w.sum, w.cnt);
     wcache_init<C>(w);
@@ -231,7 +243,7 @@ __device__ __forceinline__ void wcache_flush(WaveCache<C>& w, AccTable<C>& t, fl
 // lanes), one table update per run.
 template <int C>
 __device__ __forceinline__ void accum_update(bool pass, uint32_t pix, const float (&f)[C], AccTable<C>& t,
-                                             float* __restrict__ sums, int32_t* __restrict__ counts,
+                                             const SumsRef& sums, int32_t* __restrict__ counts,
                                              WaveCache<C>& w) {
     const uint64_t rem = ballot(pass);
     if (rem == 0) return;
@@ -270,14 +282,13 @@ __device__ __forceinline__ void acc_table_clear(AccTable<C>& t) {
 
 // Adds every occupied slot to the global sums and counts and empties it.
 template <int C>
-__device__ __forceinline__ void acc_table_flush(AccTable<C>& t, float* __restrict__ sums, int32_t* __restrict__ counts) {
+__device__ __forceinline__ void acc_table_flush(AccTable<C>& t, const SumsRef& sums, int32_t* __restrict__ counts) {
     for (int j = threadIdx.x; j < AccTable<C>::H; j += blockDim.x) {
         uint32_t k = t.key[j];
         if (k != kEmptySlot) {
-            float* dst = sums + (uint64_t)k * C;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                atomic_add_f32(dst + c, t.sum[c][j]);
+                atomic_add_f32(sum_at<C>(sums, k, c), t.sum[c][j]);
                 t.sum[c][j] = 0.f;
             }
             atomic_add_i32(counts + k, t.cnt[j]);
@@ -292,7 +303,7 @@ template <int C, bool OPTS>
 __device__ __forceinline__ uint32_t accum_point(const Cam& c, int L, float fa, bool live, float x, float y, float z,
                                             const float (&f)[C], const PointOpts& o, const PointExtra& e,
                                             const uint32_t* __restrict__ keys32, AccTable<C>& t,
-                                            float* __restrict__ sums, int32_t* __restrict__ counts, WaveCache<C>& w) {
+                                            const SumsRef& sums, int32_t* __restrict__ counts, WaveCache<C>& w) {
     Proj p = project(c, x, y, z);
     bool ok = live && p.ok;
     uint32_t lmask = 0xffu;
@@ -337,8 +348,9 @@ __global__ void __launch_bounds__(256) k_accum(const float* __restrict__ xs, con
                                                const float* __restrict__ zs, const void* __restrict__ feat,
                                                int64_t n, const ViewRec* __restrict__ views, int V, int L,
                                                int VG, float fa, PointOpts o, const uint32_t* __restrict__ keys32,
-                                               float* __restrict__ sums, int32_t* __restrict__ counts,
+                                               float* __restrict__ sums_p, int64_t P, int32_t* __restrict__ counts,
                                                uint8_t* __restrict__ vis) {
+    const SumsRef sums{sums_p, P};
     __shared__ AccTable<C> t;
     acc_table_clear<C>(t);
     __syncthreads();
@@ -391,7 +403,7 @@ struct Background {
 
 template <int C>
 __global__ void __launch_bounds__(256) k_normalize(const ViewRec* __restrict__ views, int L,
-                                                   const float* __restrict__ sums,
+                                                   const float* __restrict__ sums, int64_t P,
                                                    const int32_t* __restrict__ counts,
                                                    float* __restrict__ images, Background bg) {
     int vl = blockIdx.y;
@@ -402,11 +414,12 @@ __global__ void __launch_bounds__(256) k_normalize(const ViewRec* __restrict__ v
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < npx; j += (int64_t)gridDim.x * blockDim.x) {
         uint64_t p = base + (uint64_t)j;
         int32_t k = counts[p];
-        const float* s = sums + p * C;
+        const float* s = sums + p;          // planar [C][pixels]
+        const uint64_t cs = (uint64_t)P;   // channel stride
         float* out = images + (uint64_t)C * base + (uint64_t)j;
 #pragma unroll
         for (int ch = 0; ch < C; ++ch) {
-            float val = k > 0 ? __fdiv_rn(s[ch], (float)k) : bg.v[ch];
+            float val = k > 0 ? __fdiv_rn(s[(uint64_t)ch * cs], (float)k) : bg.v[ch];
             out[(uint64_t)ch * (uint64_t)npx] = val;
         }
     }
@@ -915,7 +928,7 @@ static void forward_points(const FwdArgs& a, hipStream_t st) {
     }
     a.timer.mark(kKAccum, 0, st);
     k_accum<C, S, OPTS><<<ga, kBlock, 0, st>>>(a.x, a.y, a.z, a.feat, a.n, a.views, a.V, a.L, vg, a.fa, a.opts,
-                                                  reinterpret_cast<const uint32_t*>(a.keys), a.sums, a.counts,
+                                                  reinterpret_cast<const uint32_t*>(a.keys), a.sums, a.pixels, a.counts,
                                                   a.vis);
     a.timer.mark(kKAccum, 1, st);
 }
@@ -930,7 +943,7 @@ static hipError_t forward_impl(const FwdArgs& a, hipStream_t st) {
     }
     dim3 gn((unsigned)std::min<int64_t>((a.max_layer_pixels + 255) / 256, 1024), (unsigned)(a.V * a.L));
     a.timer.mark(kKNormalize, 0, st);
-    k_normalize<C><<<gn, 256, 0, st>>>(a.views, a.L, a.sums, a.counts, a.images, make_bg(a.background, C));
+    k_normalize<C><<<gn, 256, 0, st>>>(a.views, a.L, a.sums, a.pixels, a.counts, a.images, make_bg(a.background, C));
     a.timer.mark(kKNormalize, 1, st);
     return hipGetLastError();
 }
