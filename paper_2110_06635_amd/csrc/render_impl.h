@@ -37,11 +37,6 @@
 
 namespace adop {
 
-// bits of the accumulation's per-workgroup LDS table for up to 4 channels
-// (one less for 5..8, two less for 9..16)
-#ifndef ADOP_ACC_BITS4
-#define ADOP_ACC_BITS4 9
-#endif
 
 // ---------------------------------------------------------------------------
 // forward
@@ -154,7 +149,10 @@ __global__ void __launch_bounds__(256) k_depth(const float* __restrict__ xs, con
 // ---- accumulation pass ----------------------------------------------------
 
 template <int C> struct AccTable {
-    static constexpr int bits = C <= 4 ? ADOP_ACC_BITS4 : (C <= 8 ? ADOP_ACC_BITS4 - 1 : ADOP_ACC_BITS4 - 2);
+    // slots of the per-workgroup LDS table: 1024 up to 4 channels (24 KB),
+    // 128 above (more slots cost the 8-channel multi-view pass occupancy
+    // and flush work than they save in global atomics)
+    static constexpr int bits = C <= 4 ? 10 : 7;
     static constexpr int H = 1 << bits;
     uint32_t key[H];
     float sum[C][H];
