@@ -100,6 +100,7 @@ class Server:
         self.rejected = 0
         self.batches = 0
         self.batch_sizes: List[int] = []
+        self.peak_inflight = 0          # most batches on the GPU at once
         self.fail_hook: Optional[Callable[[int], bool]] = None   # test hook: batch id -> fail?
 
     # ---------------------------------------------------------------- client
@@ -228,6 +229,7 @@ class Server:
                     self._used += mem
                     self._peak = max(self._peak, self._used)
                     self._inflight.append((bid, h, batch, lane))
+                    self.peak_inflight = max(self.peak_inflight, len(self._inflight))
                 self.batches += 1
                 self.batch_sizes.append(len(batch))
                 progressed = True
@@ -251,6 +253,8 @@ class Server:
                 "mean_ms": float(lat.mean() * 1e3), "renders_per_s": len(ok) / span if span > 0 else 0.0,
                 "batches": self.batches,
                 "mean_batch": float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0,
+                "max_batch": int(max(self.batch_sizes)) if self.batch_sizes else 0,
+                "peak_inflight": int(self.peak_inflight),
                 "peak_mem_bytes": int(self._peak), "per_class": per_class}
 
 

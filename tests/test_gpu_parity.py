@@ -109,6 +109,53 @@ def test_half_integer_ties(G):
     run_case(A, ctx, O, s)
 
 
+def test_distortion_foldover_cull(G):
+    """Reading Q6: points beyond the fold-over limit r2 > r2_max are culled.
+    With strong barrel distortion (k1 = -0.2) far off-axis directions fold
+    back into the frame; r2_max = 0.5 lies below the fold, so every such
+    point must be dropped by both sides (keys, counts, gradients)."""
+    A, ctx, O = G
+    rng = np.random.default_rng(71)
+    n = 40000
+    cam = synth.Camera(96, 72, 30.0, 30.0, 48.0, 36.0, k1=-0.2, r2_max=0.5)
+    ab = rng.uniform(-2.3, 2.3, (n, 2))
+    z = rng.uniform(2.0, 6.0, n)
+    pos = np.stack([ab[:, 0] * z, ab[:, 1] * z, z], axis=1).astype(np.float32)
+    feat = rng.random((n, 3)).astype(np.float32)
+    # the case is exercised: many points beyond r2_max would land in the
+    # image if they were not culled (float64 textbook projection)
+    r2 = (ab ** 2).sum(axis=1)
+    D = 1.0 - 0.2 * r2
+    u = np.rint(30.0 * ab[:, 0] * D + 48.0)
+    v = np.rint(30.0 * ab[:, 1] * D + 36.0)
+    folded = (r2 > 0.51) & (u >= 0) & (u < 96) & (v >= 0) & (v < 72)
+    assert int(folded.sum()) > 5000
+    _, _, _, valid = O.project_points(cam, pos)
+    assert not valid[folded].any() and valid[r2 < 0.49].all()
+    s = synth.Scene(pos, feat, [cam], layers=3, name="foldover")
+    say(f"fold-over cull: {int(folded.sum())} folded points, r2_max 0.5")
+    print(run_case(A, ctx, O, s))
+
+
+def test_non_finite_points(G):
+    """Reading Q27: NaN and +-Inf coordinates cull the point.  They are mixed
+    into a scene that goes through scene preparation (non-finite points sort
+    last in the Morton order) and render with zero gradients."""
+    A, ctx, O = G
+    s = small_scene(72, 20000)
+    rng = np.random.default_rng(73)
+    bad = rng.choice(s.n, 1500, replace=False)
+    vals = np.array([np.nan, np.inf, -np.inf], np.float32)
+    for k, i in enumerate(bad):
+        s.pos[i, k % 3] = vals[(k // 3) % 3]
+    assert int((~np.isfinite(s.pos)).any(axis=1).sum()) == 1500
+    say("non-finite coordinates, prepared scene")
+    print(run_case(A, ctx, O, s))
+    scene, _ = to_device_scene(A, ctx, s, "f32", True)
+    orig = scene.orig.cpu().numpy()
+    assert set(orig[-1500:].tolist()) == set(bad.tolist())   # sorted last
+
+
 @pytest.mark.parametrize("c", [1, 3, 8, 16])
 def test_channels(G, c):
     A, ctx, O = G

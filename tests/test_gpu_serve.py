@@ -24,14 +24,26 @@ def test_served_equals_alone(oracle, graphs):
                                torch.from_numpy(raw.view(np.int16)).to(dev).view(torch.bfloat16), adop.BF16)
     be = serve.GpuBackend(ctx, scene, layers=4, use_graphs=graphs)
     srv = serve.Server(be, 24 << 30, max_batch=4, max_inflight=3)
-    tr = synth.config5_requests(48, rate=400.0, seed=77)
+    # a burst queued before the scheduler starts: batches of several views
+    # are formed and several batches are on the GPU at once
+    burst = [srv.submit(cam) for _, cam in synth.config5_requests(24, seed=78)]
     srv.start()
-    reqs = serve.replay(srv, tr)
+    for r in burst:
+        assert r.done.wait(120)
+    st = srv.stats()
+    print("burst", st)
+    assert st["completed"] == len(burst) and st["failed"] == 0
+    assert st["max_batch"] > 1, "no batch held more than one view"
+    assert st["peak_inflight"] > 1, "batches never overlapped on the GPU"
+    mixed = [r for r in burst if sum(q.batch_id == r.batch_id for q in burst) > 1]
+    assert len(mixed) >= 4
+    # then a Poisson trace while the server runs
+    tr = synth.config5_requests(48, rate=400.0, seed=77)
+    reqs = burst + serve.replay(srv, tr)
     srv.stop()
     st = srv.stats()
     print(st)
-    assert st["completed"] == len(tr) and st["failed"] == 0
-    assert st["mean_batch"] >= 1.0
+    assert st["completed"] == len(reqs) and st["failed"] == 0
     worst = 0.0
     for r in reqs:
         fr = adop.render_forward(ctx, scene, [r.camera], 4)

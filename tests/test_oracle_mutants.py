@@ -14,6 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "adop_oracle.c")
 
 MICRO = {s["name"]: s for s in pins.MICRO}
+TOL = {t["name"]: t for t in pins.TOL_SCALE}
 
 # (id, original text, mutated text, check that must fail)
 MUTANTS = [
@@ -67,6 +68,31 @@ MUTANTS = [
      lambda O: nxt.test_discard_equals_rendering_each_layers_kept_subset(O)),
     ("knn_third", "radius[i] = sqrtf(best[3]);", "radius[i] = sqrtf(best[2]);",
      lambda O: nxt.test_knn_radius_against_kdtree(O)),
+    # the tolerance yardstick S: inflated or deflated magnitudes
+    ("scale_gc_inflated",
+     "(fabs(a) * ga_m + fabs(b) * gb_m) / fabs(Zd) };",
+     "(fabs(a) * ga_m + fabs(b) * gb_m + ga_m) / fabs(Zd) };",
+     lambda O: pins.test_tolerance_scale_microscenes(O, TOL["S1_empty_neighbours"])),
+    ("scale_intr_inflated",
+     "double di_m[9] = { gu_m * fabs(xd), gv_m * fabs(yd), gu_m, gv_m,",
+     "double di_m[9] = { gu_m * (fabs(xd) + 1.0), gv_m * fabs(yd), gu_m, gv_m,",
+     lambda O: pins.test_tolerance_scale_microscenes(O, TOL["S1_empty_neighbours"])),
+    ("scale_omega_inflated",
+     "double cr_m[3] = { fabs(xc[1]) * gc_m[2] + fabs(xc[2]) * gc_m[1],",
+     "double cr_m[3] = { fabs(xc[1]) * gc_m[2] + fabs(xc[2]) * gc_m[1] + gc_m[0],",
+     lambda O: pins.test_tolerance_scale_microscenes(O, TOL["S2_neighbour_in_front"])),
+    ("scale_dfeat_no_count",
+     "if (dfeat_abs) dfeat_abs[i * c + ch] += fabs(g) / k * chain;",
+     "if (dfeat_abs) dfeat_abs[i * c + ch] += fabs(g) * chain;",
+     lambda O: pins.test_tolerance_scale_microscenes(O, TOL["S4b_equal_depth_n3"])),
+    ("scale_case4_undivided",
+     "m += fabs(g) * (fabs(tau[ch]) + fabs(I)) / (double)(nq + 1);",
+     "m += fabs(g) * (fabs(tau[ch]) + fabs(I));",
+     lambda O: pins.test_tolerance_scale_microscenes(O, TOL["S4b_equal_depth_n3"])),
+    ("scale_shift_deflated",
+     "gu_m += ldexp(0.5 * (mr + ml), -l);",
+     "gu_m += ldexp(0.25 * (mr + ml), -l);",
+     lambda O: pins.test_tolerance_scale_bounds_every_entry(O, 0)),
 ]
 
 
