@@ -244,6 +244,27 @@ adop_status adop_render_forward(adop_context* ctx, const adop_scene* scene,
  *                          on the left, at xi = 0
  *   dintr [V][9] FP64   -- dL/d(fx, fy, cx, cy, k1, k2, k3, p1, p2)
  * The FP64 sums are reduced in a fixed order (run-to-run deterministic). */
+/* Allocation-free forward, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same pass as adop_render_forward, with the same frame
+ * outputs, but without a workspace argument: the per-view records and the
+ * FP32 sums live in a fixed array of ADOP_NOALLOC_SCRATCH_BYTES bytes that
+ * the library holds on every GPU it runs on until the process ends.  The
+ * call needs  256*V (rounded up to a multiple of 256)  +  pixels*C*4 (rounded
+ * up to a multiple of 256)  bytes of it, e.g. 44.2 MB at 1920x1080 with 5
+ * layers and 4 channels; a larger request fails with ADOP_E_WORKSPACE before
+ * anything is enqueued.  The call allocates nothing (no hipMalloc, no
+ * library allocation); the sums are cleared by the call itself.
+ * `stream` must belong to the context's device.  Every call on one GPU uses
+ * that GPU's single array: calls that overlap in time on one GPU (other
+ * streams, other contexts or threads) race and give wrong results; calls
+ * ordered on one stream are safe. */
+#define ADOP_NOALLOC_SCRATCH_BYTES (64u << 20)
+adop_status adop_render_forward_noalloc(adop_context* ctx, const adop_scene* scene,
+                                        const adop_camera* cams, int32_t V,
+                                        const adop_render_params* params,
+                                        const adop_frame* frame, void* stream);
+
 adop_status adop_render_backward(adop_context* ctx, const adop_scene* scene,
                                  const adop_camera* cams, int32_t V,
                                  const adop_render_params* params,

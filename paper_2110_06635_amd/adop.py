@@ -97,6 +97,8 @@ def lib():
         L.adop_knn_radius.argtypes = [P, P, P, P, I64, P, P]
         L.adop_render_forward.restype = S
         L.adop_render_forward.argtypes = [P, P, P, I32, P, P, P, ct.c_size_t, P]
+        L.adop_render_forward_noalloc.restype = S
+        L.adop_render_forward_noalloc.argtypes = [P, P, P, I32, P, P, P]
         L.adop_render_backward.restype = S
         L.adop_render_backward.argtypes = [P, P, P, I32, P, P, P, P, P, P, P, P, ct.c_size_t, P]
         L.adop_forward_graph_create.restype = S
@@ -118,7 +120,7 @@ def lib():
 EXPORTS = ["adop_version", "adop_status_string", "adop_context_create", "adop_context_destroy",
            "adop_last_error", "adop_views_layout", "adop_workspace_bytes", "adop_feature_bytes",
            "adop_scene_prepare", "adop_scene_gather", "adop_knn_radius",
-           "adop_render_forward", "adop_render_backward",
+           "adop_render_forward", "adop_render_forward_noalloc", "adop_render_backward",
            "adop_forward_graph_create", "adop_forward_graph_launch", "adop_graph_destroy",
            "adop_timing_enable", "adop_timing_read", "adop_timing_kernel_name"]
 TIMING_KERNELS = 7
@@ -385,6 +387,28 @@ def render_forward(ctx: Context, scene: Scene, cams, layers: int, alpha: float =
     st = lib().adop_render_forward(ctx.handle, ct.byref(sd), frame.cams, len(frame.cams), ct.byref(p),
                                    ct.byref(fd), _ptr(ws), ws.numel(), _stream(stream))
     ctx.check(st, "adop_render_forward")
+    return frame
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # ADOP_NOALLOC_SCRATCH_BYTES
+
+
+def render_forward_noalloc(ctx: Context, scene: Scene, frame: Frame, alpha: float = 0.01, flags: int = 0,
+                           background=None, stream=None, gamma: float = GAMMA) -> Frame:
+    """The forward pass into an existing frame (with frame.visible, if set)
+    through adop_render_forward_noalloc: no workspace, nothing allocated by
+    this call; the library's fixed per-GPU array holds the sums."""
+    C = scene.channels
+    if frame.channels != C:
+        raise ValueError("frame channels do not match the scene")
+    if frame.visible is not None and tuple(frame.visible.shape) != (len(frame.cams), scene.n):
+        raise ValueError("frame.visible does not match the scene and views")
+    p, keep = _params(frame.layers, alpha, flags, background, C, gamma)
+    sd = scene.desc()
+    fd = frame.desc()
+    st = lib().adop_render_forward_noalloc(ctx.handle, ct.byref(sd), frame.cams, len(frame.cams), ct.byref(p),
+                                           ct.byref(fd), _stream(stream))
+    ctx.check(st, "adop_render_forward_noalloc")
     return frame
 
 

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -21,6 +22,39 @@ namespace {
 
 constexpr int kSlots = 32;
 constexpr size_t kSlotBytes = (size_t)ADOP_MAX_VIEWS * sizeof(ViewRec);
+
+}  // namespace
+
+// Fixed scratch of adop_render_forward_noalloc: the per-view records and the
+// FP32 sums of the forward pass, one copy per GPU (each device that loads
+// the library holds its own instance until the process ends).  In host code
+// `scratch` only names the symbol; the device address of a GPU's instance
+// comes from hipGetSymbolAddress with that GPU current (scratch_setup).
+static_assert(ADOP_NOALLOC_SCRATCH_BYTES % 256 == 0, "scratch size must be a multiple of 256");
+static __device__ __align__(256) unsigned char scratch[ADOP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be current: looked up
+// once per device, then reused by every context on it.
+hipError_t scratch_setup(int device, void** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p || ((uintptr_t)p & 255) != 0) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 }  // namespace
 
@@ -38,6 +72,9 @@ struct adop_context {
     std::vector<Mark> marks;
     std::vector<hipEvent_t> pool;
     hipError_t timing_error = hipSuccess;
+    // device address of this GPU's instance of `scratch` (null if the lookup failed)
+    void* scratch_dev = nullptr;
+    hipError_t scratch_error = hipSuccess;
 };
 
 struct adop_graph {
@@ -138,6 +175,11 @@ int bwd_group_cap(int cus) { return std::max(8, cus * adop::kBwdGroupsPerCu / 8 
 
 size_t views_region(int32_t V) { return align256((size_t)std::max(V, 1) * sizeof(ViewRec)); }
 
+// Workspace of a forward pass alone: view records, then the FP32 sums.
+size_t forward_workspace_bytes(int32_t C, int32_t V, int64_t pixels) {
+    return views_region(V) + align256((size_t)pixels * C * sizeof(float));
+}
+
 size_t workspace_bytes(int cus, int32_t C, int32_t V, int64_t pixels) {
     size_t fwd = (size_t)pixels * C * sizeof(float);
     size_t bwd = align256((size_t)pixels * adop::pack_stride(C) * sizeof(float)) +
@@ -161,7 +203,7 @@ adop_status check_scene(adop_context* ctx, const adop_scene* s) {
 
 adop_status check_common(adop_context* ctx, const adop_scene* scene, const adop_camera* cams, int32_t V,
                          const adop_render_params* params, const adop_frame* frame, void* ws, size_t ws_bytes,
-                         int32_t vmax, int64_t* total) {
+                         int32_t vmax, int64_t* total, bool forward_only = false) {
     if (!ctx) return ADOP_E_INVALID;
     ctx->err.clear();
     adop_status s = check_scene(ctx, scene);
@@ -193,7 +235,8 @@ adop_status check_common(adop_context* ctx, const adop_scene* scene, const adop_
     if (*total >= 0x7fffffffLL || (*total) * scene->channels >= (int64_t)1 << 40)
         return fail(ctx, ADOP_E_UNSUPPORTED, "frame of %lld pixels is too large", (long long)*total);
     if (!ws) return fail(ctx, ADOP_E_WORKSPACE, "workspace is NULL");
-    size_t need = workspace_bytes(ctx->cus, scene->channels, V, *total);
+    size_t need = forward_only ? forward_workspace_bytes(scene->channels, V, *total)
+                               : workspace_bytes(ctx->cus, scene->channels, V, *total);
     if (ws_bytes < need) return fail(ctx, ADOP_E_WORKSPACE, "workspace %zu bytes < %zu", ws_bytes, need);
     if (((uintptr_t)ws & 255) != 0) return fail(ctx, ADOP_E_INVALID, "workspace must be 256-byte aligned");
     return ADOP_OK;
@@ -325,6 +368,7 @@ adop_status adop_context_create(int32_t device, adop_context** out) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         ctx->cus = prop.multiProcessorCount;
+    ctx->scratch_error = scratch_setup(device, &ctx->scratch_dev);
     if (hipHostMalloc((void**)&ctx->pinned, kSlots * kSlotBytes, hipHostMallocDefault) != hipSuccess) {
         delete ctx;
         return ADOP_E_DEVICE;
@@ -467,6 +511,43 @@ adop_status adop_render_forward(adop_context* ctx, const adop_scene* scene, cons
     if (s) return s;
     adop::FwdArgs a = fwd_args(ctx, scene, cams, V, params, frame, workspace, total);
     hipError_t e = adop::launch_forward(a, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "forward launch");
+    return ADOP_OK;
+}
+
+adop_status adop_render_forward_noalloc(adop_context* ctx, const adop_scene* scene, const adop_camera* cams,
+                                        int32_t V, const adop_render_params* params, const adop_frame* frame,
+                                        void* stream) {
+    if (!ctx) return ADOP_E_INVALID;
+    ctx->err.clear();
+    if (!ctx->scratch_dev)
+        return fail(ctx, ADOP_E_DEVICE, "no scratch array on device %d: %s (%d)", ctx->device,
+                    hipGetErrorString(ctx->scratch_error), (int)ctx->scratch_error);
+    hipStream_t st = (hipStream_t)stream;
+    int sdev = -1;
+    hipError_t e = st ? hipStreamGetDevice(st, &sdev) : hipGetDevice(&sdev);
+    if (e != hipSuccess) return hip_fail(ctx, e, "stream device");
+    if (sdev != ctx->device)
+        return fail(ctx, ADOP_E_INVALID, "stream is on device %d, the context on device %d", sdev, ctx->device);
+    if (scene && params && check_cameras(nullptr, cams, V, params->layers, ADOP_MAX_VIEWS) == ADOP_OK &&
+        scene->channels >= 1 && scene->channels <= ADOP_MAX_CHANNELS) {
+        int64_t total = 0;
+        layout(cams, V, params->layers, &total, nullptr);
+        const size_t need = forward_workspace_bytes(scene->channels, V, total);
+        if (need > (size_t)ADOP_NOALLOC_SCRATCH_BYTES)
+            return fail(ctx, ADOP_E_WORKSPACE,
+                        "allocation-free forward: %lld pyramid pixels x %d channels need %zu scratch bytes, "
+                        "more than the fixed %zu",
+                        (long long)total, scene->channels, need, (size_t)ADOP_NOALLOC_SCRATCH_BYTES);
+    }
+    int64_t total = 0;
+    adop_status s = check_common(ctx, scene, cams, V, params, frame, ctx->scratch_dev, ADOP_NOALLOC_SCRATCH_BYTES,
+                                 ADOP_MAX_VIEWS, &total, true);
+    if (s) return s;
+    s = stage_views(ctx, cams, V, params->layers, ctx->scratch_dev, st);
+    if (s) return s;
+    adop::FwdArgs a = fwd_args(ctx, scene, cams, V, params, frame, ctx->scratch_dev, total);
+    e = adop::launch_forward(a, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "forward launch");
     return ADOP_OK;
 }
