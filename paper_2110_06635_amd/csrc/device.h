@@ -67,6 +67,16 @@ __device__ __forceinline__ Cam load_cam(const ViewRec* __restrict__ v) {
     return c;
 }
 
+// Layer loops run to a compile-time bound: kernels are compiled for a fixed
+// layer count LN (4 and 5, the pyramid depths of the paper's renders) and for
+// any count (LN = 0: up to kMaxLayers with a run-time stop at L).  With a
+// fixed count a point's per-layer work is straight-line code, its per-layer
+// gathers stay in flight together and its layer arrays stay in registers.
+template <int LN> struct Layers {
+    static constexpr int max = LN > 0 ? LN : kMaxLayers;
+    static __device__ __forceinline__ bool has(int l, int L) { return LN > 0 ? true : l < L; }
+};
+
 // Layer scale 2^-l as an exact constant.
 __device__ __forceinline__ float layer_scale(int l) {
     return __int_as_float((127 - l) << 23);

@@ -13,19 +13,29 @@ void launch_clear(const FwdArgs& a, int64_t nsums, hipStream_t st) {
     a.timer.mark(kKClear, 1, st);
 }
 
-template <bool SINGLE, bool OPTS>
+template <bool SINGLE, bool OPTS, int LN>
 static void depth_pass(const FwdArgs& a, hipStream_t st) {
-    static const int occ = resident(k_depth<SINGLE, OPTS>, 0);
+    static const int occ = resident(k_depth<SINGLE, OPTS, LN>, 0);
     unsigned gd = persistent_grid(a.n, kBlock, a.cus, occ, 1 << 20);
     if (!SINGLE) gd = range_grid(a.n, kDepthViewRange, gd);
-    k_depth<SINGLE, OPTS><<<gd, kBlock, 0, st>>>(a.x, a.y, a.z, a.orig, a.n, a.views, a.V, a.L, a.opts, a.keys);
+    k_depth<SINGLE, OPTS, LN><<<gd, kBlock, 0, st>>>(a.x, a.y, a.z, a.orig, a.n, a.views, a.V, a.L, a.fa, a.opts,
+                                                    a.keys, a.vis);
+}
+
+template <bool SINGLE, bool OPTS>
+static void depth_layers(const FwdArgs& a, hipStream_t st) {
+    switch (a.L) {
+        case 4: return depth_pass<SINGLE, OPTS, 4>(a, st);
+        case 5: return depth_pass<SINGLE, OPTS, 5>(a, st);
+        default: return depth_pass<SINGLE, OPTS, 0>(a, st);
+    }
 }
 
 void launch_depth(const FwdArgs& a, hipStream_t st) {
     const bool opts = a.opts.flags & (kOptCullBack | kOptCullPrinted | kOptDiscard);
     a.timer.mark(kKDepth, 0, st);
-    if (a.V == 1) opts ? depth_pass<true, true>(a, st) : depth_pass<true, false>(a, st);
-    else opts ? depth_pass<false, true>(a, st) : depth_pass<false, false>(a, st);
+    if (a.V == 1) opts ? depth_layers<true, true>(a, st) : depth_layers<true, false>(a, st);
+    else opts ? depth_layers<false, true>(a, st) : depth_layers<false, false>(a, st);
     a.timer.mark(kKDepth, 1, st);
 }
 

@@ -60,10 +60,16 @@ __global__ void __launch_bounds__(256) k_clear(uint64_t* __restrict__ keys, int3
 #endif  // ADOP_RENDER_BASE
 
 // ---- depth pass -----------------------------------------------------------
-template <bool OPTS>
-__device__ __forceinline__ void depth_point(const Cam& c, int L, bool live, float x, float y, float z, uint32_t oi,
-                                            const PointOpts& o, const PointExtra& e,
-                                            uint64_t* __restrict__ keys) {
+// Returns the point's candidate layers: bit l is set when the point lies in
+// layer l's bounds and is not yet behind the front depth read at its pixel
+// by more than the fuzzy margin.  The front depth only falls, so a point
+// with z > fl((1+alpha) z_read) >= fl((1+alpha) min_z) fails the fuzzy
+// depth test of the accumulation pass there (Eq. depthtest, monotone FP32
+// rounding): the bits are a superset of the layers where it blends.
+template <bool OPTS, int LN>
+__device__ __forceinline__ uint32_t depth_point(const Cam& c, int L, float fa, bool live, float x, float y, float z,
+                                                uint32_t oi, const PointOpts& o, const PointExtra& e,
+                                                uint64_t* __restrict__ keys) {
     Proj p = project(c, x, y, z);
     bool ok = live && p.ok;
     uint32_t lmask = 0xffu;
@@ -72,23 +78,34 @@ __device__ __forceinline__ void depth_point(const Cam& c, int L, bool live, floa
         if (ok) lmask = discard_mask(o, c, p, e, L);
     }
     uint64_t key = ((uint64_t)__float_as_uint(p.Z) << 32) | oi;
-    uint32_t pix[kMaxLayers];
-    bool in[kMaxLayers];
-    uint64_t cur[kMaxLayers];
+    uint32_t pix[Layers<LN>::max];
+    bool in[Layers<LN>::max];
+    uint64_t cur[Layers<LN>::max];
 #pragma unroll
-    for (int l = 0; l < kMaxLayers; ++l) {
+    for (int l = 0; l < Layers<LN>::max; ++l) {
         pix[l] = 0;
         in[l] = false;
         cur[l] = 0;
-        if (l < L) {
+        if (Layers<LN>::has(l, L)) {
             int px = 0, py = 0;
             in[l] = layer_pixel(c, ok, l, p.u0, p.v0, px, py, pix[l]) && ((lmask >> l) & 1u);
             cur[l] = load_relaxed_u64(keys + pix[l]);   // pix is valid for every lane
         }
     }
+    // keep the L gathers in flight together: nothing that uses them is
+    // scheduled between them
+    __builtin_amdgcn_sched_barrier(0);
+    uint32_t cand = 0;
 #pragma unroll
-    for (int l = 0; l < kMaxLayers; ++l) {
-        if (l >= L) break;
+    for (int l = 0; l < Layers<LN>::max; ++l) {
+        if (!Layers<LN>::has(l, L)) break;
+        // an empty key reads as NaN depth: the point stays a candidate
+        const float zr = __uint_as_float(__builtin_bit_cast(vu2, cur[l]).y);
+        cand |= (uint32_t)(in[l] && !(p.Z > __fmul_rn(zr, fa))) << l;
+    }
+#pragma unroll
+    for (int l = 0; l < Layers<LN>::max; ++l) {
+        if (!Layers<LN>::has(l, L)) break;
         bool want = in[l] && key < cur[l];
         uint64_t m = ballot(want);
         if (m == 0) continue;
@@ -103,15 +120,19 @@ __device__ __forceinline__ void depth_point(const Cam& c, int L, bool live, floa
             if (run_min_u64(want ? pix[l] : kEmptySlot, kEmptySlot, k)) atomic_min_u64(keys + pix[l], k);
         }
     }
+    return cand;
 }
 
 #ifdef ADOP_RENDER_BASE
-// OPTS: compiled with the optional per-point inputs (culling, discarding)
-template <bool SINGLE, bool OPTS>
+// OPTS: compiled with the optional per-point inputs (culling, discarding).
+// cand (optional, [V][n]): the candidate layers of every point and view,
+// read and overwritten by the accumulation pass.
+template <bool SINGLE, bool OPTS, int LN>
 __global__ void __launch_bounds__(256) k_depth(const float* __restrict__ xs, const float* __restrict__ ys,
                                                const float* __restrict__ zs, const int32_t* __restrict__ orig,
                                                int64_t n, const ViewRec* __restrict__ views, int V, int L,
-                                               PointOpts o, uint64_t* __restrict__ keys) {
+                                               float fa, PointOpts o, uint64_t* __restrict__ keys,
+                                               uint8_t* __restrict__ cand) {
     const Cam c0 = load_cam(views);
     RangeMap m = range_map(n, kBlock);
     // the next chunk's points are loaded while the current one is processed
@@ -137,10 +158,15 @@ __global__ void __launch_bounds__(256) k_depth(const float* __restrict__ xs, con
         const uint32_t oi = noi;
         const PointExtra e = ne;
         if (c + 1 < m.c1) fetch(c + 1);
+        const uint64_t i = (uint64_t)(c * kBlock + threadIdx.x);
         if (SINGLE) {
-            depth_point<OPTS>(c0, L, live, x, y, z, oi, o, e, keys);
+            const uint32_t cm = depth_point<OPTS, LN>(c0, L, fa, live, x, y, z, oi, o, e, keys);
+            if (cand != nullptr && live) cand[i] = (uint8_t)cm;
         } else {
-            for (int v = 0; v < V; ++v) depth_point<OPTS>(load_cam(views + v), L, live, x, y, z, oi, o, e, keys);
+            for (int v = 0; v < V; ++v) {
+                const uint32_t cm = depth_point<OPTS, LN>(load_cam(views + v), L, fa, live, x, y, z, oi, o, e, keys);
+                if (cand != nullptr && live) cand[(uint64_t)v * (uint64_t)n + i] = (uint8_t)cm;
+            }
         }
     }
 }
@@ -297,38 +323,41 @@ __device__ __forceinline__ void acc_table_flush(AccTable<C>& t, const SumsRef& s
 }
 
 // Returns the blend-set bits of the point (bit l: it passed at layer l).
-template <int C, bool OPTS>
-__device__ __forceinline__ uint32_t accum_point(const Cam& c, int L, float fa, bool live, float x, float y, float z,
-                                            const float (&f)[C], const PointOpts& o, const PointExtra& e,
-                                            const uint32_t* __restrict__ keys32, AccTable<C>& t,
-                                            const SumsRef& sums, int32_t* __restrict__ counts, WaveCache<C>& w) {
+// cand: the point's candidate layers from the depth pass (0xff without).
+template <int C, bool OPTS, int LN>
+__device__ __forceinline__ uint32_t accum_point(const Cam& c, int L, float fa, bool live, uint32_t cand, float x,
+                                                float y, float z, const float (&f)[C], const PointOpts& o,
+                                                const PointExtra& e, const uint32_t* __restrict__ keys32,
+                                                AccTable<C>& t, const SumsRef& sums, int32_t* __restrict__ counts,
+                                                WaveCache<C>& w) {
     Proj p = project(c, x, y, z);
     bool ok = live && p.ok;
-    uint32_t lmask = 0xffu;
+    uint32_t lmask = cand;
     if (OPTS && (o.flags & (kOptCullBack | kOptCullPrinted | kOptDiscard))) {
         ok = ok && normal_kept(o, c, p, e);
-        if (ok) lmask = discard_mask(o, c, p, e, L);
+        if (ok) lmask &= discard_mask(o, c, p, e, L);
     }
     // all layers' front depths are gathered before any update, so the
-    // gathers are in flight together
-    uint32_t pix[kMaxLayers];
-    bool in[kMaxLayers];
-    float mz[kMaxLayers];
+    // gathers are in flight together; a lane outside a layer (or no
+    // candidate there) loads nothing for it
+    uint32_t pix[Layers<LN>::max];
+    bool in[Layers<LN>::max];
+    float mz[Layers<LN>::max];
 #pragma unroll
-    for (int l = 0; l < kMaxLayers; ++l) {
+    for (int l = 0; l < Layers<LN>::max; ++l) {
         pix[l] = 0;
         in[l] = false;
         mz[l] = 0.f;
-        if (l < L) {
+        if (Layers<LN>::has(l, L)) {
             int px = 0, py = 0;
             in[l] = layer_pixel(c, ok, l, p.u0, p.v0, px, py, pix[l]) && ((lmask >> l) & 1u);
-            mz[l] = __uint_as_float(keys32[2 * (uint64_t)pix[l] + 1]);   // pix is valid for every lane
+            if (in[l]) mz[l] = __uint_as_float(keys32[2 * (uint64_t)pix[l] + 1]);
         }
     }
     uint32_t seen = 0;
 #pragma unroll
-    for (int l = 0; l < kMaxLayers; ++l) {
-        if (l >= L) break;
+    for (int l = 0; l < Layers<LN>::max; ++l) {
+        if (!Layers<LN>::has(l, L)) break;
         bool pass = in[l] && p.Z <= __fmul_rn(mz[l], fa);
         seen |= (uint32_t)pass << l;
         accum_update<C>(pass, pix[l], f, t, sums, counts, w);
@@ -341,7 +370,7 @@ __device__ __forceinline__ uint32_t accum_point(const Cam& c, int L, float fa, b
 // kAccumViewGroup), so every workgroup's table and wave cache see one view's
 // pixels, and the workgroups of a range in one group read its points while
 // they are in the caches.
-template <int C, typename S, bool OPTS>
+template <int C, typename S, bool OPTS, int LN>
 __global__ void __launch_bounds__(256) k_accum(const float* __restrict__ xs, const float* __restrict__ ys,
                                                const float* __restrict__ zs, const void* __restrict__ feat,
                                                int64_t n, const ViewRec* __restrict__ views, int V, int L,
@@ -357,16 +386,26 @@ __global__ void __launch_bounds__(256) k_accum(const float* __restrict__ xs, con
     int view = 0;
     RangeMap m = V > 1 ? view_range_map(n, kBlock, V, VG, view) : range_map(n, kBlock);
     const Cam c0 = load_cam(views + view);
+    // With blend-set bits requested, vis holds the depth pass's candidate
+    // layers on entry (read two chunks ahead): a point without any cannot
+    // blend anywhere, so its position and features are not loaded, it is not
+    // projected, and a wave without candidates only writes its zero bits.
+    uint8_t* const vrow = vis != nullptr ? vis + (uint64_t)view * (uint64_t)n : nullptr;
+    auto fetch_cand = [&](int64_t cc) -> uint32_t {
+        const int64_t i = cc * kBlock + threadIdx.x;
+        return (vrow != nullptr && i < n) ? (uint32_t)vrow[i] : 0xffu;
+    };
     // the next chunk's points are loaded while the current one is processed
     float nx = 0.f, ny = 0.f, nz = 0.f, nf[C];
 #pragma unroll
     for (int ch = 0; ch < C; ++ch) nf[ch] = 0.f;
     bool nlive = false;
+    uint32_t ncand = 0xffu, ncand2 = 0xffu;   // candidates of chunks c + 1 and c + 2
     PointExtra ne;
     auto fetch = [&](int64_t c) {
         int64_t i = c * kBlock + threadIdx.x;
         nlive = i < n;
-        if (nlive) {
+        if (nlive && ncand != 0) {
             nx = ld_nt(xs + i);
             ny = ld_nt(ys + i);
             nz = ld_nt(zs + i);
@@ -374,21 +413,34 @@ __global__ void __launch_bounds__(256) k_accum(const float* __restrict__ xs, con
             if (OPTS) load_extra(o, i, ne);
         }
     };
-    if (m.c0 < m.c1) fetch(m.c0);
+    if (m.c0 < m.c1) {
+        ncand = fetch_cand(m.c0);
+        fetch(m.c0);
+    }
+    if (m.c0 + 1 < m.c1) ncand2 = fetch_cand(m.c0 + 1);
     for (int64_t c = m.c0; c < m.c1; ++c) {
         const bool live = nlive;
+        const uint32_t cand = ncand;
         const float x = nx, y = ny, z = nz;
         float f[C];
 #pragma unroll
         for (int ch = 0; ch < C; ++ch) f[ch] = nf[ch];
         const PointExtra e = ne;
+        ncand = ncand2;
         if (c + 1 < m.c1) fetch(c + 1);
+        if (c + 2 < m.c1) ncand2 = fetch_cand(c + 2);
+        const uint64_t i = (uint64_t)(c * kBlock + threadIdx.x);
+        if (ballot(live && cand != 0) == 0) {
+            if (vrow != nullptr && live) vrow[i] = 0;
+            continue;
+        }
         if (OPTS && (o.flags & kOptLog)) {
 #pragma unroll
             for (int ch = 0; ch < C; ++ch) f[ch] = expf(f[ch]);
         }
-        const uint32_t seen = accum_point<C, OPTS>(c0, L, fa, live, x, y, z, f, o, e, keys32, t, sums, counts, w);
-        if (vis != nullptr && live) vis[(uint64_t)view * (uint64_t)n + (uint64_t)(c * kBlock + threadIdx.x)] = (uint8_t)seen;
+        const uint32_t seen = accum_point<C, OPTS, LN>(c0, L, fa, live && cand != 0, cand, x, y, z, f, o, e, keys32, t,
+                                                   sums, counts, w);
+        if (vrow != nullptr && live) vrow[i] = (uint8_t)seen;
     }
     wcache_flush<C>(w, t, sums, counts);
     __syncthreads();
@@ -541,10 +593,10 @@ __device__ __forceinline__ void layer_work(const float* __restrict__ pack, uint3
 // kVisUnknown to test the point against the records here.
 constexpr uint32_t kVisUnknown = 0xffffffffu;
 
-template <int C, bool OPTS>
+template <int C, bool OPTS, int LN>
 __device__ __forceinline__ void point_view(const Cam& c, int L, float fa, bool spatial_all,
                                            const float* __restrict__ pack, bool live, float x, float y, float z,
-                                           const float (&tau)[C], float (&dt)[C], float (&dp)[3], float (&acc)[15],
+                                           const float (&tau)[C], float (&dt)[C], float (&dp)[3], double (&acc)[15],
                                            bool& any, const PointOpts& o, const PointExtra& e, uint32_t known) {
     using PL = PackLayout<C>;
     if (known == 0) return;   // in no blend set: no gradient (known only without SPATIAL_ALL)
@@ -562,13 +614,13 @@ __device__ __forceinline__ void point_view(const Cam& c, int L, float fa, bool s
         }
         work = 0;
         seen = 0;
-        float mz[kMaxLayers];
-        bool in[kMaxLayers];
+        float mz[Layers<LN>::max];
+        bool in[Layers<LN>::max];
 #pragma unroll
-        for (int l = 0; l < kMaxLayers; ++l) {
+        for (int l = 0; l < Layers<LN>::max; ++l) {
             mz[l] = 0.f;
             in[l] = false;
-            if (l < L) {
+            if (Layers<LN>::has(l, L)) {
                 int qx = 0, qy = 0;
                 uint32_t pix = 0;
                 in[l] = layer_pixel(c, true, l, p.u0, p.v0, qx, qy, pix) && ((lmask >> l) & 1u);
@@ -576,7 +628,7 @@ __device__ __forceinline__ void point_view(const Cam& c, int L, float fa, bool s
             }
         }
 #pragma unroll
-        for (int l = 0; l < kMaxLayers; ++l) {
+        for (int l = 0; l < Layers<LN>::max; ++l) {
             const bool vis = in[l] && p.Z <= mz[l];   // Eq. depthtest against (1+alpha) min_z
             seen |= (uint32_t)vis << l;
             work |= (uint32_t)(vis || (spatial_all && in[l])) << l;
@@ -616,38 +668,30 @@ __device__ __forceinline__ void point_view(const Cam& c, int L, float fa, bool s
     dp[2] += c.R[2] * gcx + c.R[5] * gcy + c.R[8] * gcz;
     const float au = gux * a + gvy * b;
     const float r4 = r2 * r2;
-    acc[0] += gcx;
-    acc[1] += gcy;
-    acc[2] += gcz;
-    acc[3] += p.Y * gcz - p.Z * gcy;
-    acc[4] += p.Z * gcx - p.X * gcz;
-    acc[5] += p.X * gcy - p.Y * gcx;
-    acc[6] += gu * p.xd;
-    acc[7] += gv * p.yd;
-    acc[8] += gu;
-    acc[9] += gv;
-    acc[10] += au * r2;
-    acc[11] += au * r4;
-    acc[12] += au * r4 * r2;
-    acc[13] += gux * 2.0f * a * b + gvy * (r2 + 2.0f * b * b);
-    acc[14] += gux * (r2 + 2.0f * a * a) + gvy * 2.0f * a * b;
+    // the point's 15 pose/intrinsics terms in FP32, each widened to FP64
+    // before it is added
+    const float term[15] = {gcx, gcy, gcz,
+                            p.Y * gcz - p.Z * gcy, p.Z * gcx - p.X * gcz, p.X * gcy - p.Y * gcx,
+                            gu * p.xd, gv * p.yd, gu, gv,
+                            au * r2, au * r4, au * r4 * r2,
+                            gux * 2.0f * a * b + gvy * (r2 + 2.0f * b * b),
+                            gux * (r2 + 2.0f * a * a) + gvy * 2.0f * a * b};
+#pragma unroll
+    for (int t = 0; t < 15; ++t) acc[t] += (double)term[t];
 }
 
-// The 15 terms of the PPL points of a lane (FP32, at most PPL terms each) are
-// widened to FP64 and summed over the wave in a fixed DPP order; each wave
-// owns its LDS slot, so the sum order is fixed for a fixed grid.
-__device__ __forceinline__ void reduce_terms(const float (&acc)[15], bool any, double* __restrict__ slot, int lane) {
+// FP64 sums of the 15 terms over the wave (fixed DPP order); lane 0 adds
+// them to the wave's own LDS slot, so the order is fixed for a fixed grid.
+__device__ __forceinline__ void reduce_terms(const double (&acc)[15], bool any, double* __restrict__ slot, int lane) {
     if (ballot(any) == 0) return;
 #pragma unroll
     for (int t = 0; t < 15; ++t) {
-        double s = wave_sum_f64((double)acc[t]);
+        double s = wave_sum_f64(acc[t]);
         if (lane == 0) slot[t] += s;
     }
 }
 
-constexpr int kSuper = 4;   // chunks a lane sums in FP32 before widening (single view)
-
-template <int C, typename S, int PPL, bool SINGLE, bool OPTS>
+template <int C, typename S, int PPL, bool SINGLE, bool OPTS, int LN>
 __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, const float* __restrict__ ys,
                                                   const float* __restrict__ zs, const void* __restrict__ feat,
                                                   int64_t n, const ViewRec* __restrict__ views, int V, int L,
@@ -655,23 +699,24 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
                                                   const float* __restrict__ pack,
                                                   float* __restrict__ dfeat, float* __restrict__ dpos,
                                                   double* __restrict__ partials, const uint8_t* __restrict__ vis) {
-    // single view: [256 lanes][16] FP64 per-lane sums; several views:
-    // [4 waves][V][16] per-wave sums
+    // several views: [4 waves][V][16] per-wave FP64 sums (dynamic LDS)
     extern __shared__ double acc_lds[];
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
-    const int slots = SINGLE ? kBlock * 16 : 4 * V * 16;
-    for (int j = threadIdx.x; j < slots; j += blockDim.x) acc_lds[j] = 0.0;
-    __syncthreads();
+    if (!SINGLE) {
+        for (int j = threadIdx.x; j < 4 * V * 16; j += blockDim.x) acc_lds[j] = 0.0;
+        __syncthreads();
+    }
     const bool spatial_all = (flags & 1u) != 0;
     // the forward's blend-set bits replace the tests (not with SPATIAL_ALL,
     // which needs every in-bounds point)
     const bool use_vis = vis != nullptr && !spatial_all;
     const Cam c0 = load_cam(views);
-    float acc1[15];
+    // single view: every lane's FP64 sums of its points' terms, in the
+    // order the lane visits them
+    double acc1[15];
 #pragma unroll
-    for (int t = 0; t < 15; ++t) acc1[t] = 0.f;
-    int since = 0;
+    for (int t = 0; t < 15; ++t) acc1[t] = 0.0;
 
     RangeMap m = range_map(n, (int64_t)kBlock * PPL);
     // single view: the blend-set bits of the next chunk are loaded one chunk
@@ -720,30 +765,21 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
             bool any = false;
 #pragma unroll
             for (int k = 0; k < PPL; ++k)
-                point_view<C, OPTS>(c0, L, fa, spatial_all, pack, live[k], px_[k], py_[k], pz_[k], tau[k], dt[k], dp[k],
+                point_view<C, OPTS, LN>(c0, L, fa, spatial_all, pack, live[k], px_[k], py_[k], pz_[k], tau[k], dt[k], dp[k],
                               acc1, any, o, ex[k], known[k]);
-            if (++since == kSuper || c + 1 == m.c1) {
-                double* slot = acc_lds + threadIdx.x * 16;
-#pragma unroll
-                for (int t = 0; t < 15; ++t) {
-                    slot[t] += (double)acc1[t];
-                    acc1[t] = 0.f;
-                }
-                since = 0;
-            }
         } else {
             for (int v = 0; v < V; ++v) {
                 const Cam cv = load_cam(views + v);
-                float acc[15];
+                double acc[15];
 #pragma unroll
-                for (int t = 0; t < 15; ++t) acc[t] = 0.f;
+                for (int t = 0; t < 15; ++t) acc[t] = 0.0;
                 bool any = false;
 #pragma unroll
                 for (int k = 0; k < PPL; ++k) {
                     const int64_t i = wbase + (int64_t)k * kWave + lane;
                     const uint32_t kn = (use_vis && live[k]) ? (uint32_t)vis[(uint64_t)v * (uint64_t)n + (uint64_t)i]
                                                              : kVisUnknown;
-                    point_view<C, OPTS>(cv, L, fa, spatial_all, pack, live[k], px_[k], py_[k], pz_[k], tau[k], dt[k],
+                    point_view<C, OPTS, LN>(cv, L, fa, spatial_all, pack, live[k], px_[k], py_[k], pz_[k], tau[k], dt[k],
                                   dp[k], acc, any, o, ex[k], kn);
                 }
                 reduce_terms(acc, any, acc_lds + (wave * V + v) * 16, lane);
@@ -763,22 +799,23 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
             st_nt(dpos + 2 * n + i, dp[k][2]);
         }
     }
-    __syncthreads();
     if (SINGLE) {
-        // fixed-order sum of the 256 lanes' FP64 partials: 16 threads per
-        // term each sum 16 lanes, then one thread sums the 16 results
-        __shared__ double red[16][16];
-        const int t = threadIdx.x & 15, part = threadIdx.x >> 4;
-        double s = 0.0;
-        for (int j = 0; j < 16; ++j) s += acc_lds[(part * 16 + j) * 16 + t];
-        red[part][t] = s;
+        // fixed-order FP64 sums: each wave's lanes (DPP tree), then the four
+        // waves in order
+        __shared__ double wsum[4][16];
+#pragma unroll
+        for (int t = 0; t < 15; ++t) {
+            const double s = wave_sum_f64(acc1[t]);
+            if (lane == 0) wsum[wave][t] = s;
+        }
         __syncthreads();
         if (threadIdx.x < 16) {
-            double r = 0.0;
-            for (int j = 0; j < 16; ++j) r += red[j][threadIdx.x];
-            partials[(uint64_t)blockIdx.x * 16 + threadIdx.x] = r;
+            const int t = threadIdx.x;
+            partials[(uint64_t)blockIdx.x * 16 + t] =
+                t < 15 ? ((wsum[0][t] + wsum[1][t]) + wsum[2][t]) + wsum[3][t] : 0.0;
         }
     } else {
+        __syncthreads();
         for (int j = threadIdx.x; j < V * 16; j += blockDim.x) {
             double s = 0.0;
             for (int w = 0; w < 4; ++w) s += acc_lds[w * V * 16 + j];
@@ -908,10 +945,9 @@ void launch_clear(const FwdArgs& a, int64_t nsums, hipStream_t st);
 void launch_depth(const FwdArgs& a, hipStream_t st);
 void launch_reduce(const BwdArgs& a, unsigned groups, hipStream_t st);
 
-template <int C, typename S, bool SINGLE, bool OPTS>
-static void forward_points(const FwdArgs& a, hipStream_t st) {
-    static const int occ_accum = resident(k_accum<C, S, OPTS>, 0);
-    launch_depth(a, st);
+template <int C, typename S, bool SINGLE, bool OPTS, int LN>
+static void accum_pass(const FwdArgs& a, hipStream_t st) {
+    static const int occ_accum = resident(k_accum<C, S, OPTS, LN>, 0);
     unsigned ga;
     int vg = a.V;
     if (SINGLE) {
@@ -925,10 +961,20 @@ static void forward_points(const FwdArgs& a, hipStream_t st) {
         vg = std::min(a.V, kAccumViewGroup);
     }
     a.timer.mark(kKAccum, 0, st);
-    k_accum<C, S, OPTS><<<ga, kBlock, 0, st>>>(a.x, a.y, a.z, a.feat, a.n, a.views, a.V, a.L, vg, a.fa, a.opts,
-                                                  reinterpret_cast<const uint32_t*>(a.keys), a.sums, a.pixels, a.counts,
-                                                  a.vis);
+    k_accum<C, S, OPTS, LN><<<ga, kBlock, 0, st>>>(a.x, a.y, a.z, a.feat, a.n, a.views, a.V, a.L, vg, a.fa, a.opts,
+                                                      reinterpret_cast<const uint32_t*>(a.keys), a.sums, a.pixels,
+                                                      a.counts, a.vis);
     a.timer.mark(kKAccum, 1, st);
+}
+
+// Fixed layer counts 4 and 5 for the plain path; the optional per-point
+// inputs take the any-count kernel.
+template <int C, typename S, bool SINGLE, bool OPTS>
+static void forward_points(const FwdArgs& a, hipStream_t st) {
+    launch_depth(a, st);
+    if (!OPTS && a.L == 4) accum_pass<C, S, SINGLE, OPTS, 4>(a, st);
+    else if (!OPTS && a.L == 5) accum_pass<C, S, SINGLE, OPTS, 5>(a, st);
+    else accum_pass<C, S, SINGLE, OPTS, 0>(a, st);
 }
 
 template <int C, typename S>
@@ -946,20 +992,27 @@ static hipError_t forward_impl(const FwdArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <int C, typename S, bool SINGLE, bool OPTS>
-static unsigned backward_points(const BwdArgs& a, hipStream_t st) {
+template <int C, typename S, bool SINGLE, bool OPTS, int LN>
+static unsigned backward_pass(const BwdArgs& a, hipStream_t st) {
     constexpr int PPL = bwd_points_per_lane<C, S>();
-    const size_t lds = SINGLE ? (size_t)kBlock * 16 * sizeof(double) : (size_t)4 * a.V * 16 * sizeof(double);
-    static const int occ = resident(k_backward<C, S, PPL, SINGLE, OPTS>,
-                                    SINGLE ? lds : (size_t)4 * kMaxViewsBwd * 16 * sizeof(double));
+    const size_t lds = SINGLE ? 0 : (size_t)4 * a.V * 16 * sizeof(double);
+    static const int occ = resident(k_backward<C, S, PPL, SINGLE, OPTS, LN>,
+                                    SINGLE ? 0 : (size_t)4 * kMaxViewsBwd * 16 * sizeof(double));
     unsigned g = persistent_grid(a.n, (int64_t)kBlock * PPL, a.cus, occ, a.groups);
     g = std::min<unsigned>(range_grid(a.n, kBackwardRange, g), (unsigned)a.groups / kXcds * kXcds);
     a.timer.mark(kKBackward, 0, st);
-    k_backward<C, S, PPL, SINGLE, OPTS><<<g, kBlock, lds, st>>>(a.x, a.y, a.z, a.feat, a.n, a.views, a.V, a.L, a.fa,
-                                                          a.flags, a.opts, a.pack, a.dfeat, a.dpos, a.partials,
-                                                          a.vis);
+    k_backward<C, S, PPL, SINGLE, OPTS, LN><<<g, kBlock, lds, st>>>(a.x, a.y, a.z, a.feat, a.n, a.views, a.V, a.L,
+                                                                     a.fa, a.flags, a.opts, a.pack, a.dfeat, a.dpos,
+                                                                     a.partials, a.vis);
     a.timer.mark(kKBackward, 1, st);
     return g;
+}
+
+template <int C, typename S, bool SINGLE, bool OPTS>
+static unsigned backward_points(const BwdArgs& a, hipStream_t st) {
+    if (!OPTS && a.L == 4) return backward_pass<C, S, SINGLE, OPTS, 4>(a, st);
+    if (!OPTS && a.L == 5) return backward_pass<C, S, SINGLE, OPTS, 5>(a, st);
+    return backward_pass<C, S, SINGLE, OPTS, 0>(a, st);
 }
 
 template <int C, typename S>
