@@ -124,6 +124,11 @@ __device__ __forceinline__ uint32_t depth_point(const Cam& c, int L, float fa, b
 }
 
 #ifdef ADOP_RENDER_BASE
+#ifndef ADOP_DEPTH_SAMPLE
+#define ADOP_DEPTH_SAMPLE 8
+#endif
+constexpr int64_t kDepthSample = ADOP_DEPTH_SAMPLE;   // sample stride of the depth pass's chunk order
+static_assert(kDepthSample >= 2, "sample stride");
 // OPTS: compiled with the optional per-point inputs (culling, discarding).
 // cand (optional, [V][n]): the candidate layers of every point and view,
 // read and overwritten by the accumulation pass.
@@ -151,13 +156,27 @@ __global__ void __launch_bounds__(256) k_depth(const float* __restrict__ xs, con
             if (OPTS) load_extra(o, i, ne);
         }
     };
-    if (m.c0 < m.c1) fetch(m.c0);
-    for (int64_t c = m.c0; c < m.c1; ++c) {
+    // Chunk order: first every kDepthSample-th chunk of the range (a sample
+    // spread over its region), then the others in order.  The minimum does
+    // not depend on the order, but once every workgroup has done its sample
+    // the keys hold nearly the final fronts, so the later points mostly find
+    // themselves behind them: fewer atomics here and fewer candidates for the
+    // accumulation pass.
+    const int64_t len = m.c1 - m.c0;
+    const int64_t q = (len + kDepthSample - 1) / kDepthSample;
+    auto chunk_at = [&](int64_t j) -> int64_t {
+        if (j < q) return m.c0 + j * kDepthSample;
+        j -= q;   // j-th chunk whose offset is not a multiple of kDepthSample
+        return m.c0 + j + j / (kDepthSample - 1) + 1;
+    };
+    if (len > 0) fetch(chunk_at(0));
+    for (int64_t j = 0; j < len; ++j) {
+        const int64_t c = chunk_at(j);
         const bool live = nlive;
         const float x = nx, y = ny, z = nz;
         const uint32_t oi = noi;
         const PointExtra e = ne;
-        if (c + 1 < m.c1) fetch(c + 1);
+        if (j + 1 < len) fetch(chunk_at(j + 1));
         const uint64_t i = (uint64_t)(c * kBlock + threadIdx.x);
         if (SINGLE) {
             const uint32_t cm = depth_point<OPTS, LN>(c0, L, fa, live, x, y, z, oi, o, e, keys);
@@ -593,10 +612,10 @@ __device__ __forceinline__ void layer_work(const float* __restrict__ pack, uint3
 // kVisUnknown to test the point against the records here.
 constexpr uint32_t kVisUnknown = 0xffffffffu;
 
-template <int C, bool OPTS, int LN>
+template <int C, bool OPTS, int LN, typename Terms>
 __device__ __forceinline__ void point_view(const Cam& c, int L, float fa, bool spatial_all,
                                            const float* __restrict__ pack, bool live, float x, float y, float z,
-                                           const float (&tau)[C], float (&dt)[C], float (&dp)[3], double (&acc)[15],
+                                           const float (&tau)[C], float (&dt)[C], float (&dp)[3], Terms& acc,
                                            bool& any, const PointOpts& o, const PointExtra& e, uint32_t known) {
     using PL = PackLayout<C>;
     if (known == 0) return;   // in no blend set: no gradient (known only without SPATIAL_ALL)
@@ -676,17 +695,37 @@ __device__ __forceinline__ void point_view(const Cam& c, int L, float fa, bool s
                             au * r2, au * r4, au * r4 * r2,
                             gux * 2.0f * a * b + gvy * (r2 + 2.0f * b * b),
                             gux * (r2 + 2.0f * a * a) + gvy * 2.0f * a * b};
-#pragma unroll
-    for (int t = 0; t < 15; ++t) acc[t] += (double)term[t];
+    acc.add(term);
 }
+
+// Where a point's 15 pose/intrinsics terms go (each widened to FP64 before
+// it is added).  One view: the lane's own FP64 slots in LDS, a [15][256]
+// array with one column per lane (consecutive lanes hit consecutive banks,
+// no two lanes share a slot, and a lane adds its points in its own order).
+// Several views: FP64 registers per view, summed over the wave afterwards.
+struct LdsTerms {
+    double* col;   // &slots[0][threadIdx.x]
+    __device__ __forceinline__ void add(const float (&term)[15]) {
+#pragma unroll
+        for (int t = 0; t < 15; ++t)
+            __hip_atomic_fetch_add(col + t * kBlock, (double)term[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+};
+struct RegTerms {
+    double v[15];
+    __device__ __forceinline__ void add(const float (&term)[15]) {
+#pragma unroll
+        for (int t = 0; t < 15; ++t) v[t] += (double)term[t];
+    }
+};
 
 // FP64 sums of the 15 terms over the wave (fixed DPP order); lane 0 adds
 // them to the wave's own LDS slot, so the order is fixed for a fixed grid.
-__device__ __forceinline__ void reduce_terms(const double (&acc)[15], bool any, double* __restrict__ slot, int lane) {
+__device__ __forceinline__ void reduce_terms(const RegTerms& acc, bool any, double* __restrict__ slot, int lane) {
     if (ballot(any) == 0) return;
 #pragma unroll
     for (int t = 0; t < 15; ++t) {
-        double s = wave_sum_f64(acc[t]);
+        double s = wave_sum_f64(acc.v[t]);
         if (lane == 0) slot[t] += s;
     }
 }
@@ -699,88 +738,117 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
                                                   const float* __restrict__ pack,
                                                   float* __restrict__ dfeat, float* __restrict__ dpos,
                                                   double* __restrict__ partials, const uint8_t* __restrict__ vis) {
-    // several views: [4 waves][V][16] per-wave FP64 sums (dynamic LDS)
+    // one view: [15][256] per-lane FP64 slots; several views: [4 waves][V][16]
+    // per-wave FP64 sums (dynamic LDS)
     extern __shared__ double acc_lds[];
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
-    if (!SINGLE) {
-        for (int j = threadIdx.x; j < 4 * V * 16; j += blockDim.x) acc_lds[j] = 0.0;
-        __syncthreads();
-    }
+    const int slots = SINGLE ? 15 * kBlock : 4 * V * 16;
+    for (int j = threadIdx.x; j < slots; j += blockDim.x) acc_lds[j] = 0.0;
+    __syncthreads();
     const bool spatial_all = (flags & 1u) != 0;
     // the forward's blend-set bits replace the tests (not with SPATIAL_ALL,
     // which needs every in-bounds point)
     const bool use_vis = vis != nullptr && !spatial_all;
     const Cam c0 = load_cam(views);
-    // single view: every lane's FP64 sums of its points' terms, in the
-    // order the lane visits them
-    double acc1[15];
-#pragma unroll
-    for (int t = 0; t < 15; ++t) acc1[t] = 0.0;
+    LdsTerms lterms{acc_lds + threadIdx.x};
 
     RangeMap m = range_map(n, (int64_t)kBlock * PPL);
-    // single view: the blend-set bits of the next chunk are loaded one chunk
-    // ahead, so a point that blends nowhere needs neither its position nor
-    // its features and its loads are not issued
-    uint32_t known_next[PPL];
-    auto fetch_known = [&](int64_t cc) {
+    auto index = [&](int64_t cc, int k) -> int64_t {
+        return cc * kBlock * PPL + (int64_t)wave * kWave * PPL + (int64_t)k * kWave + lane;
+    };
+    // One view: the blend-set bits are loaded two chunks ahead and the
+    // positions and features one chunk ahead, only for points with bits
+    // (a point that blends nowhere costs its bit load and its zero stores).
+    uint32_t kn1[PPL], kn2[PPL];   // bits of chunks c + 1 and c + 2
+    float nx[PPL], ny[PPL], nz[PPL], nf[PPL][C];
+    PointExtra nex[PPL];
+    auto bits = [&](int64_t cc, int k) -> uint32_t {
+        const int64_t i = index(cc, k);
+        return (SINGLE && use_vis && i < n) ? (uint32_t)vis[i] : kVisUnknown;
+    };
+    auto fetch = [&](int64_t cc) {
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
-            const int64_t i = cc * kBlock * PPL + (int64_t)wave * kWave * PPL + (int64_t)k * kWave + lane;
-            known_next[k] = (SINGLE && use_vis && i < n) ? (uint32_t)vis[i] : kVisUnknown;
+            const int64_t i = index(cc, k);
+            if (i < n && kn1[k] != 0) {
+                nx[k] = ld_nt(xs + i);
+                ny[k] = ld_nt(ys + i);
+                nz[k] = ld_nt(zs + i);
+                load_feat<C, S>(feat, i, nf[k]);
+                if (OPTS) load_extra(o, i, nex[k]);
+            }
         }
     };
-    if (m.c0 < m.c1) fetch_known(m.c0);
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        kn1[k] = kn2[k] = kVisUnknown;
+        nx[k] = ny[k] = nz[k] = 0.f;
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch) nf[k][ch] = 0.f;
+    }
+    if (m.c0 < m.c1) {
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) kn1[k] = bits(m.c0, k);
+        fetch(m.c0);
+    }
+    if (m.c0 + 1 < m.c1) {
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) kn2[k] = bits(m.c0 + 1, k);
+    }
     for (int64_t c = m.c0; c < m.c1; ++c) {
-        const int64_t wbase = c * kBlock * PPL + (int64_t)wave * kWave * PPL;
         float px_[PPL], py_[PPL], pz_[PPL];
         float tau[PPL][C], dt[PPL][C], dp[PPL][3];
         bool live[PPL];
         PointExtra ex[PPL];
         uint32_t known[PPL];
 #pragma unroll
-        for (int k = 0; k < PPL; ++k) known[k] = known_next[k];
-        if (c + 1 < m.c1) fetch_known(c + 1);
-#pragma unroll
         for (int k = 0; k < PPL; ++k) {
-            int64_t i = wbase + (int64_t)k * kWave + lane;
-            live[k] = i < n;
-            px_[k] = py_[k] = pz_[k] = 0.f;
+            known[k] = kn1[k];
+            live[k] = index(c, k) < n;
+            px_[k] = nx[k];
+            py_[k] = ny[k];
+            pz_[k] = nz[k];
+            ex[k] = nex[k];
 #pragma unroll
-            for (int ch = 0; ch < C; ++ch) { tau[k][ch] = 0.f; dt[k][ch] = 0.f; }
-            dp[k][0] = dp[k][1] = dp[k][2] = 0.f;
-            if (live[k] && known[k] != 0) {
-                px_[k] = ld_nt(xs + i);
-                py_[k] = ld_nt(ys + i);
-                pz_[k] = ld_nt(zs + i);
-                load_feat<C, S>(feat, i, tau[k]);
-                if (OPTS) load_extra(o, i, ex[k]);
+            for (int ch = 0; ch < C; ++ch) {
+                tau[k][ch] = nf[k][ch];
+                dt[k][ch] = 0.f;
             }
-            if (OPTS && (o.flags & kOptLog)) {   // logarithmic descriptors render as exp(f)
+            dp[k][0] = dp[k][1] = dp[k][2] = 0.f;
+            kn1[k] = kn2[k];
+        }
+        if (c + 1 < m.c1) fetch(c + 1);
+        if (c + 2 < m.c1) {
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) kn2[k] = bits(c + 2, k);
+        }
+        if (OPTS && (o.flags & kOptLog)) {   // logarithmic descriptors render as exp(f)
+#pragma unroll
+            for (int k = 0; k < PPL; ++k)
 #pragma unroll
                 for (int ch = 0; ch < C; ++ch) tau[k][ch] = expf(tau[k][ch]);
-            }
         }
         if (SINGLE) {
             bool any = false;
 #pragma unroll
             for (int k = 0; k < PPL; ++k)
-                point_view<C, OPTS, LN>(c0, L, fa, spatial_all, pack, live[k], px_[k], py_[k], pz_[k], tau[k], dt[k], dp[k],
-                              acc1, any, o, ex[k], known[k]);
+                point_view<C, OPTS, LN>(c0, L, fa, spatial_all, pack, live[k], px_[k], py_[k], pz_[k], tau[k],
+                                        dt[k], dp[k], lterms, any, o, ex[k], known[k]);
         } else {
             for (int v = 0; v < V; ++v) {
                 const Cam cv = load_cam(views + v);
-                double acc[15];
+                RegTerms acc;
 #pragma unroll
-                for (int t = 0; t < 15; ++t) acc[t] = 0.0;
+                for (int t = 0; t < 15; ++t) acc.v[t] = 0.0;
                 bool any = false;
 #pragma unroll
                 for (int k = 0; k < PPL; ++k) {
-                    const int64_t i = wbase + (int64_t)k * kWave + lane;
+                    const int64_t i = index(c, k);
                     const uint32_t kn = (use_vis && live[k]) ? (uint32_t)vis[(uint64_t)v * (uint64_t)n + (uint64_t)i]
                                                              : kVisUnknown;
-                    point_view<C, OPTS, LN>(cv, L, fa, spatial_all, pack, live[k], px_[k], py_[k], pz_[k], tau[k], dt[k],
-                                  dp[k], acc, any, o, ex[k], kn);
+                    point_view<C, OPTS, LN>(cv, L, fa, spatial_all, pack, live[k], px_[k], py_[k], pz_[k], tau[k],
+                                            dt[k], dp[k], acc, any, o, ex[k], kn);
                 }
                 reduce_terms(acc, any, acc_lds + (wave * V + v) * 16, lane);
             }
@@ -788,7 +856,7 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
             if (!live[k]) continue;
-            int64_t i = wbase + (int64_t)k * kWave + lane;
+            const int64_t i = index(c, k);
             if (OPTS && (o.flags & kOptLog)) {   // d exp(f) / df = exp(f)
 #pragma unroll
                 for (int ch = 0; ch < C; ++ch) dt[k][ch] *= tau[k][ch];
@@ -799,13 +867,14 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
             st_nt(dpos + 2 * n + i, dp[k][2]);
         }
     }
+    __syncthreads();
     if (SINGLE) {
-        // fixed-order FP64 sums: each wave's lanes (DPP tree), then the four
-        // waves in order
+        // fixed-order FP64 sums: each wave's 64 lane columns (DPP tree),
+        // then the four waves in order
         __shared__ double wsum[4][16];
 #pragma unroll
         for (int t = 0; t < 15; ++t) {
-            const double s = wave_sum_f64(acc1[t]);
+            const double s = wave_sum_f64(acc_lds[t * kBlock + threadIdx.x]);
             if (lane == 0) wsum[wave][t] = s;
         }
         __syncthreads();
@@ -815,7 +884,6 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
                 t < 15 ? ((wsum[0][t] + wsum[1][t]) + wsum[2][t]) + wsum[3][t] : 0.0;
         }
     } else {
-        __syncthreads();
         for (int j = threadIdx.x; j < V * 16; j += blockDim.x) {
             double s = 0.0;
             for (int w = 0; w < 4; ++w) s += acc_lds[w * V * 16 + j];
@@ -925,11 +993,11 @@ constexpr int64_t kDepthViewRange = 4096;   // depth pass, several views
 constexpr int kAccumViewGroup = 4;
 constexpr int64_t kBackwardRange = 4096;    // backward
 // Points per lane and chunk of the backward (their loads are issued
-// together): four for FP32 features up to 4 channels, two otherwise
-// (registers; the 16-bit types convert on load)
-template <int C, typename S> constexpr int bwd_points_per_lane() {
-    return (C <= 4 && std::is_same<S, F32>::value) ? 4 : 2;
-}
+// together, one chunk ahead): two for every channel count and storage type
+// (112 VGPRs at C = 4, 4 waves per SIMD; one point per lane gives 5 waves
+// per SIMD but is slower: the two points' gathers are independent work for
+// the same wave).
+template <int C, typename S> constexpr int bwd_points_per_lane() { return 2; }
 
 // Grid of ranges of `range` points, a multiple of 8 and at least at_least.
 static inline unsigned range_grid(int64_t n, int64_t range, unsigned at_least) {
@@ -995,9 +1063,9 @@ static hipError_t forward_impl(const FwdArgs& a, hipStream_t st) {
 template <int C, typename S, bool SINGLE, bool OPTS, int LN>
 static unsigned backward_pass(const BwdArgs& a, hipStream_t st) {
     constexpr int PPL = bwd_points_per_lane<C, S>();
-    const size_t lds = SINGLE ? 0 : (size_t)4 * a.V * 16 * sizeof(double);
+    const size_t lds = SINGLE ? (size_t)15 * kBlock * sizeof(double) : (size_t)4 * a.V * 16 * sizeof(double);
     static const int occ = resident(k_backward<C, S, PPL, SINGLE, OPTS, LN>,
-                                    SINGLE ? 0 : (size_t)4 * kMaxViewsBwd * 16 * sizeof(double));
+                                    SINGLE ? lds : (size_t)4 * kMaxViewsBwd * 16 * sizeof(double));
     unsigned g = persistent_grid(a.n, (int64_t)kBlock * PPL, a.cus, occ, a.groups);
     g = std::min<unsigned>(range_grid(a.n, kBackwardRange, g), (unsigned)a.groups / kXcds * kXcds);
     a.timer.mark(kKBackward, 0, st);
