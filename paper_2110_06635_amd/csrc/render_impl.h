@@ -993,11 +993,11 @@ constexpr int64_t kDepthViewRange = 4096;   // depth pass, several views
 constexpr int kAccumViewGroup = 4;
 constexpr int64_t kBackwardRange = 4096;    // backward
 // Points per lane and chunk of the backward (their loads are issued
-// together, one chunk ahead): two for every channel count and storage type
-// (112 VGPRs at C = 4, 4 waves per SIMD; one point per lane gives 5 waves
-// per SIMD but is slower: the two points' gathers are independent work for
-// the same wave).
-template <int C, typename S> constexpr int bwd_points_per_lane() { return 2; }
+// together, one chunk ahead).  One view: two (112 VGPRs at C = 4, 4 waves
+// per SIMD; one point per lane gives 5 waves per SIMD but is slower: the two
+// points' gathers are independent work for the same wave).  Several views:
+// one (the per-view FP64 sums take registers of their own).
+template <bool SINGLE> constexpr int bwd_points_per_lane() { return SINGLE ? 2 : 1; }
 
 // Grid of ranges of `range` points, a multiple of 8 and at least at_least.
 static inline unsigned range_grid(int64_t n, int64_t range, unsigned at_least) {
@@ -1062,7 +1062,7 @@ static hipError_t forward_impl(const FwdArgs& a, hipStream_t st) {
 
 template <int C, typename S, bool SINGLE, bool OPTS, int LN>
 static unsigned backward_pass(const BwdArgs& a, hipStream_t st) {
-    constexpr int PPL = bwd_points_per_lane<C, S>();
+    constexpr int PPL = bwd_points_per_lane<SINGLE>();
     const size_t lds = SINGLE ? (size_t)15 * kBlock * sizeof(double) : (size_t)4 * a.V * 16 * sizeof(double);
     static const int occ = resident(k_backward<C, S, PPL, SINGLE, OPTS, LN>,
                                     SINGLE ? lds : (size_t)4 * kMaxViewsBwd * 16 * sizeof(double));
