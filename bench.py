@@ -101,36 +101,77 @@ def l1_grad(frame, target):
     return G
 
 
-def cpu_baseline(scene_np, n_sample):
-    """The CPU oracle (single-threaded C) on an i.i.d. prefix of the scene."""
+def host_cpu():
+    """Host CPU model name and logical CPU count."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
+def cpu_baseline(scene_np, n_sample, n_per_thread):
+    """The CPU oracle (single-threaded C, unchanged) on the host: one thread
+    on an i.i.d. prefix of the scene, then every usable core at once, each
+    thread rendering (forward + backward) its own i.i.d. slice of the scene
+    through the same oracle call (ctypes releases the interpreter lock), and
+    the aggregate points/s."""
+    import threading
     import numpy as np
     from oracle import oracle as O
     from paper_2110_06635_amd import synth
-    pos = np.ascontiguousarray(scene_np.pos[:n_sample])
-    feat = np.ascontiguousarray(scene_np.feat[:n_sample])
     total = O.total_pixels(scene_np.cams, scene_np.layers)
-    G = synth.upstream_grad(total * feat.shape[1], 99)
+    G = synth.upstream_grad(total * scene_np.feat.shape[1], 99)
+
+    def render(lo, hi):
+        pos = np.ascontiguousarray(scene_np.pos[lo:hi])
+        feat = np.ascontiguousarray(scene_np.feat[lo:hi])
+        O.forward(pos, feat, scene_np.cams, scene_np.layers, alpha=scene_np.alpha)
+        O.backward(pos, feat, scene_np.cams, scene_np.layers, G, alpha=scene_np.alpha, want_abs=False)
+
     t0 = time.perf_counter()
-    O.forward(pos, feat, scene_np.cams, scene_np.layers, alpha=scene_np.alpha)
-    O.backward(pos, feat, scene_np.cams, scene_np.layers, G, alpha=scene_np.alpha, want_abs=False)
-    dt = time.perf_counter() - t0
-    return {"value": n_sample / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
-            "seconds": dt,
-            "sample": f"{n_sample} points (i.i.d. prefix of the same scene), 1920x1080, "
-                      f"L={scene_np.layers}, forward + backward (the backward recomputes the "
-                      f"forward), float64 oracle, one thread"}
+    render(0, n_sample)
+    dt1 = time.perf_counter() - t0
+    model, ncpu = host_cpu()
+    threads = max(1, min(16, ncpu, scene_np.n // max(1, n_per_thread)))
+    ths = [threading.Thread(target=render, args=(k * n_per_thread, (k + 1) * n_per_thread))
+           for k in range(threads)]
+    t0 = time.perf_counter()
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    dtm = time.perf_counter() - t0
+    desc = (f"1920x1080, L={scene_np.layers}, forward + backward (the backward recomputes the "
+            f"forward), float64 oracle")
+    return {"value": threads * n_per_thread / dtm, "unit": "points/s", "cores": threads, "kind": "oracle",
+            "seconds": dtm,
+            "sample": f"{threads} threads at once, each {n_per_thread} points (its own i.i.d. slice of the "
+                      f"same scene), {desc}; aggregate points/s",
+            "single_thread": {"value": n_sample / dt1, "unit": "points/s", "cores": 1, "seconds": dt1,
+                              "sample": f"{n_sample} points (i.i.d. prefix of the same scene), {desc}"},
+            "cpu_model": model, "logical_cpus": ncpu}
 
 
-def serve_bench(args):
-    """Serving: a resident 50M-point BF16 scene, Poisson arrivals of
-    mixed-resolution novel views; the continuous-batching graph server vs
-    the plain unbatched FP32 renderer on the same trace."""
+def serving_leg(n_points, requests, warmup, rates, max_batch=4, budget_gib=96, seed_scene=1005,
+                max_inflight=3, candidates=True):
+    """Serving: a resident BF16 scene, Poisson arrivals of mixed-resolution
+    novel views at each rate in `rates`; the continuous-batching graph server
+    (mixed-class fused batches, slots counted against the memory budget) vs
+    the plain unbatched FP32 renderer on the same trace.  Returns a dict per
+    rate plus the workload description."""
+    import itertools
     import numpy as np
     import torch
     from paper_2110_06635_amd import adop, serve, synth
     dev = torch.device("cuda:0")
     t0 = time.time()
-    s = synth.config5_scene(n=args.serve_points)
+    s = synth.config5_scene(n=n_points, seed=seed_scene)
     log(f"generated {s.name} in {time.time() - t0:.1f}s")
     ctx = adop.Context(0)
     pos = torch.from_numpy(s.pos).to(dev)
@@ -139,43 +180,64 @@ def serve_bench(args):
                                  adop.BF16)
     scene32 = adop.Scene.prepare(ctx, pos, torch.from_numpy(s.feat).to(dev), adop.F32)
     del pos
-    trace = synth.config5_requests(args.serve_warmup + args.serve_requests, rate=args.serve_rate)
-    results = {}
-    for name, scene, be_cls, kw in (
-            ("batched", scene16, serve.GpuBackend, dict(max_batch=args.serve_batch, max_inflight=3)),
-            ("plain_fp32", scene32, serve.PlainBackend, dict(max_batch=1, max_inflight=1))):
-        be = be_cls(ctx, scene, layers=4)
-        # each frame is released once its completion is recorded, as a
-        # client consuming the stream would
-        srv = serve.Server(be, args.serve_budget_gib << 30, keep_results=False, **kw)
-        # capture every (class, batch size, lane) slot before the trace
-        for (w, h) in synth.SERVE_CLASSES:
-            cam = synth.serve_camera(np.random.default_rng(1), w, h)
-            for b in range(1, kw["max_batch"] + 1):
-                for lane in range(kw["max_inflight"]):
-                    hnd = be.launch((w, h), [cam] * b, lane)
-                    be.finish(hnd)
-        torch.cuda.synchronize()
-        srv.start()
-        log(f"serving {name}: {len(trace)} requests at {args.serve_rate}/s")
-        reqs = serve.replay(srv, trace, warmup=args.serve_warmup)
-        srv.stop()
-        measured = {r.rid for r in reqs}
-        srv.completed = [r for r in srv.completed if r.rid in measured]
-        results[name] = srv.stats()
-        del srv, be, reqs
-        torch.cuda.empty_cache()
-    b, p = results["batched"], results["plain_fp32"]
+    out = {"workload": s.name, "points": s.n, "layers": 4, "classes": synth.SERVE_CLASSES,
+           "class_weights": synth.SERVE_WEIGHTS, "requests": requests, "warmup": warmup,
+           "max_batch": max_batch, "max_inflight": max_inflight, "candidates": candidates,
+           "budget_bytes": budget_gib << 30, "rates": {}}
+    combos = [c for b in range(1, max_batch + 1)
+              for c in itertools.combinations_with_replacement(synth.SERVE_CLASSES, b)]
+    for rate in rates:
+        trace = synth.config5_requests(warmup + requests, rate=rate)
+        res = {}
+        for name, scene, be_cls, kw in (
+                ("batched", scene16, serve.GpuBackend, dict(max_batch=max_batch, max_inflight=max_inflight)),
+                ("plain_fp32", scene32, serve.PlainBackend, dict(max_batch=1, max_inflight=1))):
+            be = (serve.GpuBackend(ctx, scene, layers=4, candidates=candidates) if be_cls is serve.GpuBackend
+                  else be_cls(ctx, scene, layers=4))
+            torch.cuda.reset_peak_memory_stats(dev)
+            base = torch.cuda.memory_allocated(dev)
+            # frames are released once their completion is recorded, as a
+            # client consuming the stream would
+            srv = serve.Server(be, budget_gib << 30, keep_results=False, **kw)
+            # capture a slot for every class multiset before the trace (the
+            # server evicts idle slots if they outgrow the budget)
+            for combo in (combos if kw["max_batch"] > 1 else [(k,) for k in synth.SERVE_CLASSES]):
+                srv.prewarm(combo)
+            torch.cuda.synchronize()
+            srv.start()
+            log(f"serving {name}: {len(trace)} requests at {rate}/s")
+            reqs = serve.replay(srv, trace, warmup=warmup)
+            srv.stop()
+            measured = {r.rid for r in reqs}
+            srv.completed = [r for r in srv.completed if r.rid in measured]
+            st = srv.stats()
+            st["device_peak_allocated_bytes"] = int(torch.cuda.max_memory_allocated(dev) - base)
+            res[name] = st
+            srv.close()
+            del srv, be, reqs
+            torch.cuda.empty_cache()
+        b, p = res["batched"], res["plain_fp32"]
+        res["p99_speedup_vs_plain"] = p["p99_ms"] / b["p99_ms"] if b["p99_ms"] > 0 else None
+        res["p50_speedup_vs_plain"] = p["p50_ms"] / b["p50_ms"] if b["p50_ms"] > 0 else None
+        out["rates"][f"{rate:g}_per_s"] = res
+    del scene16, scene32
+    torch.cuda.empty_cache()
+    return out
+
+
+def serve_bench(args):
+    """The serving benchmark alone (--serve): full trace."""
+    res = serving_leg(args.serve_points, args.serve_requests, args.serve_warmup,
+                      [args.serve_rate] + ([args.serve_rate_high] if args.serve_rate_high > 0 else []),
+                      max_batch=args.serve_batch, budget_gib=args.serve_budget_gib)
+    first = res["rates"][f"{args.serve_rate:g}_per_s"]
     line = {
-        "metric": "p99 render latency, mixed-resolution novel views (50M points resident, 200 req/s)",
-        "value": b["p99_ms"], "unit": "ms", "higher_is_better": False, "n_gpus": 1,
+        "metric": f"p99 render latency, mixed-resolution novel views ({args.serve_points} points resident, "
+                  f"{args.serve_rate:g} req/s)",
+        "value": first["batched"]["p99_ms"], "unit": "ms", "higher_is_better": False, "n_gpus": 1,
         "data": "synthetic", "dtype": "bf16 features, f32 accumulation",
-        "config": {"workload": s.name, "points": s.n, "layers": 4, "classes": synth.SERVE_CLASSES,
-                   "class_weights": synth.SERVE_WEIGHTS, "rate_per_s": args.serve_rate,
-                   "requests": args.serve_requests, "warmup": args.serve_warmup,
-                   "max_batch": args.serve_batch},
-        "batched": b, "baseline_plain_fp32_unbatched": p,
-        "p99_speedup_vs_plain": p["p99_ms"] / b["p99_ms"] if b["p99_ms"] > 0 else None,
+        "config": {k: v for k, v in res.items() if k != "rates"},
+        "rates": res["rates"],
     }
     print(json.dumps(line), flush=True)
 
@@ -192,12 +254,20 @@ def main():
     ap.add_argument("--dtype", default="", choices=["", "f32", "bf16", "f16"])
     ap.add_argument("--variants", default="bf16,f16", help="extra feature storage types to time")
     ap.add_argument("--cpu-sample", type=int, default=4_000_000)
+    ap.add_argument("--cpu-sample-mt", type=int, default=1_000_000,
+                    help="points per thread of the all-cores oracle run")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve", action="store_true", help="run the serving benchmark instead")
     ap.add_argument("--serve-points", type=int, default=50_000_000)
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-warmup", type=int, default=500)
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-rate-high", type=float, default=2000.0,
+                    help="a second, saturating arrival rate (0: none)")
+    ap.add_argument("--no-serve-leg", action="store_true",
+                    help="skip the short serving leg of the default run")
+    ap.add_argument("--leg-requests", type=int, default=1500, help="measured requests per rate in the serving leg")
+    ap.add_argument("--leg-warmup", type=int, default=100)
     ap.add_argument("--serve-batch", type=int, default=4)
     ap.add_argument("--serve-budget-gib", type=int, default=96)
     ap.add_argument("--discard", action="store_true",
@@ -351,8 +421,14 @@ def main():
                         "step_frac_of_hbm_roofline": round(sum(abv.values()) / (rv["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     cpu = None
     if not args.no_cpu and V == 1 and not options:
-        log(f"cpu baseline on {args.cpu_sample} points")
-        cpu = cpu_baseline(s, args.cpu_sample)
+        log(f"cpu baseline on {args.cpu_sample} points, then all cores")
+        cpu = cpu_baseline(s, args.cpu_sample, args.cpu_sample_mt)
+    serving = None
+    if args.workload == "gmm100m" and not options and not args.no_serve_leg:
+        s.pos, s.feat = s.pos[:0], s.feat[:0]   # free the 100M-point arrays; the line uses only names
+        serving = serving_leg(args.serve_points, args.leg_requests, args.leg_warmup,
+                              [args.serve_rate] + ([args.serve_rate_high] if args.serve_rate_high > 0 else []),
+                              max_batch=args.serve_batch, budget_gib=args.serve_budget_gib)
     line = {
         "metric": ("points/sec fwd+bwd at 100M pts 1080p (% HBM roofline); p99 render latency"
                    if args.workload == "gmm100m" else f"point-views/sec fwd+bwd ({args.workload})"),
@@ -383,6 +459,7 @@ def main():
         "blends": r["blends"],
         "preprocess": r["pre"],
         "precision_variants": variants,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
 

@@ -445,12 +445,17 @@ class ForwardGraph:
     cameras of the same sizes are staged on every launch."""
 
     def __init__(self, ctx: Context, scene: Scene, cams, layers: int, alpha: float = 0.01, flags: int = 0,
-                 background=None, gamma: float = GAMMA):
+                 background=None, gamma: float = GAMMA, record_visibility: bool = False):
+        """record_visibility: the frame carries a [V, n] byte buffer, so the
+        depth pass's candidate layers let the accumulation skip points that
+        cannot blend (and the blend-set bits are left in frame.visible)."""
         self.ctx = ctx
         self.scene = scene
         C = scene.channels
         self.frame = Frame(cams, layers, C, scene.x.device)
         V = len(self.frame.cams)
+        if record_visibility:
+            self.frame.visible = torch.empty((V, scene.n), dtype=torch.uint8, device=scene.x.device)
         need = ctx.workspace_bytes(C, V, self.frame.pixels)
         self.ws = torch.empty(need, dtype=torch.uint8, device=scene.x.device)
         p, keep = _params(layers, alpha, flags, background, C, gamma)
@@ -468,8 +473,14 @@ class ForwardGraph:
         self.ctx.check(st, "adop_forward_graph_launch")
         return self.frame
 
-    def __del__(self):
+    def close(self):
+        """Destroy the graph (waits for its last launch) and drop its buffers."""
         h = getattr(self, "handle", None)
         if h is not None and _LIB is not None:
             _LIB.adop_graph_destroy(h)
-            self.handle = None
+        self.handle = None
+        self.frame = None
+        self.ws = None
+
+    def __del__(self):
+        self.close()

@@ -3,25 +3,34 @@
 One scheduler thread owns the GPU work:
   * requests (a camera each) wait in a FIFO queue, stamped with their
     scheduled arrival time;
-  * a batch is formed from the oldest request and the following requests of
-    the same resolution class (up to `max_batch`) whose output memory fits in
-    the free part of the memory budget; it is launched as ONE fused
-    multi-view forward (every point is read once and projected into all the
-    batch's views) by replaying a HIP graph captured for (class, batch size);
+  * a batch is formed from the oldest request and the requests after it (of
+    any resolution class, or of the head's class only with
+    mix_classes=False), up to `max_batch`, as long as its memory fits the
+    budget; it is launched as ONE fused multi-view forward (every point is
+    read once per pass and projected into all the batch's views) on a batch
+    slot: a HIP graph captured for the batch's multiset of classes, with its
+    frame and workspace;
   * up to `max_inflight` batches run at once, each on its own stream, so a
-    batch is admitted while others are still on the GPU; a finished batch's
-    images are copied to per-request tensors and its graph buffers are
-    reused;
+    batch is admitted while others are still on the GPU;
   * a render call that fails fails only the requests of its batch;
   * with keep_results=False a request's images are released as soon as its
     completion is recorded (a client that consumes each frame as it
-    arrives), so a long trace does not accumulate output memory.
-Latency is measured from the scheduled arrival to the moment the host sees
-the batch's completion event.
+    arrives).
 
-The GPU specifics live in `GpuBackend`; `Server` only schedules, so its
-policies (admission by memory, batching, failure isolation) are testable on
-the CPU with a fake backend.
+Memory.  The budget bounds everything the server holds on the device:
+  * every cached batch slot, idle or busy, from its creation until it is
+    evicted (idle slots are kept for reuse and evicted least recently used
+    first when a new slot would not fit);
+  * the output images of every request from its launch until its completion
+    is recorded (with keep_results=True the client owns them afterwards).
+A batch is admitted only if its outputs and, when no idle slot of its class
+multiset exists, a new slot fit after evicting idle slots.  A single request
+that cannot fit even in an empty server is rejected.
+
+Latency is measured from the scheduled arrival to the moment the host sees
+the batch's completion event.  The GPU specifics live in `GpuBackend`;
+`Server` only schedules, so its policies (admission and eviction by memory,
+batching, failure isolation) are testable on the CPU with a fake backend.
 """
 from __future__ import annotations
 
@@ -33,12 +42,15 @@ from typing import Any, Callable, Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
+Klass = Tuple[int, int]
+Combo = Tuple[Klass, ...]
+
 
 @dataclasses.dataclass
 class Request:
     rid: int
     camera: Any
-    klass: Tuple[int, int]
+    klass: Klass
     arrival: float                 # scheduled arrival (time.perf_counter base)
     out_bytes: int = 0
     done: threading.Event = dataclasses.field(default_factory=threading.Event)
@@ -52,26 +64,43 @@ class Request:
         return self.t_done - self.arrival
 
 
+@dataclasses.dataclass
+class _Slot:
+    combo: Combo
+    handle: Any
+    nbytes: int
+    busy: bool = False
+    last_use: int = 0
+
+
 class Backend:
-    """Interface the scheduler drives."""
+    """Interface the scheduler drives.  A slot holds the device buffers of a
+    fused render of one multiset of classes (`combo`, sorted); views are
+    always passed in the order of their sorted classes."""
 
-    def out_bytes(self, klass) -> int:
+    def out_bytes(self, klass: Klass) -> int:
         raise NotImplementedError
 
-    def slot_bytes(self, klass, batch: int) -> int:
-        """Device memory of one reusable batch slot (frame + workspace)."""
+    def slot_bytes(self, combo: Combo) -> int:
+        """Device memory of one batch slot for `combo` (frame + workspace)."""
         raise NotImplementedError
 
-    def launch(self, klass, cams: Sequence, lane: int) -> Any:
-        """Enqueue a fused forward of `cams` on execution lane `lane`; return
-        a handle for poll()/finish()."""
+    def create_slot(self, combo: Combo) -> Any:
+        raise NotImplementedError
+
+    def destroy_slot(self, slot: Any) -> None:
+        pass
+
+    def launch(self, slot: Any, cams: Sequence, lane: int) -> Any:
+        """Enqueue a fused forward of `cams` (sorted by class, matching the
+        slot) on execution lane `lane`; return a handle for poll()/finish()."""
         raise NotImplementedError
 
     def poll(self, handle) -> bool:
         raise NotImplementedError
 
     def finish(self, handle) -> List[Any]:
-        """Per-view results of a completed launch."""
+        """Per-view results of a completed launch, in launch order."""
         raise NotImplementedError
 
     def release(self, handle) -> None:
@@ -80,18 +109,23 @@ class Backend:
 
 class Server:
     def __init__(self, backend: Backend, mem_budget_bytes: int, max_batch: int = 8,
-                 max_inflight: int = 3, idle_sleep: float = 50e-6, keep_results: bool = True):
+                 max_inflight: int = 3, idle_sleep: float = 50e-6, keep_results: bool = True,
+                 mix_classes: bool = True):
         self.backend = backend
         self.keep_results = keep_results
+        self.mix_classes = mix_classes
         self.budget = int(mem_budget_bytes)
         self.max_batch = max_batch
         self.max_inflight = max_inflight
         self.idle_sleep = idle_sleep
         self._q: "collections.deque[Request]" = collections.deque()
         self._lock = threading.Lock()
-        self._inflight: List[Tuple[int, Any, List[Request], int]] = []
-        self._used = 0
+        self._inflight: List[Tuple[int, Any, List[Request], int, _Slot]] = []
+        self._slots: List[_Slot] = []
+        self._slot_mem = 0              # bytes of every cached slot
+        self._out_mem = 0               # bytes of outputs not yet handed over
         self._peak = 0
+        self._tick = 0
         self._next_id = 0
         self._next_batch = 0
         self._stop = False
@@ -100,6 +134,9 @@ class Server:
         self.rejected = 0
         self.batches = 0
         self.batch_sizes: List[int] = []
+        self.mixed_batches = 0          # batches holding more than one class
+        self.evictions = 0
+        self.slots_created = 0
         self.peak_inflight = 0          # most batches on the GPU at once
         self.fail_hook: Optional[Callable[[int], bool]] = None   # test hook: batch id -> fail?
 
@@ -111,7 +148,7 @@ class Server:
             rid = self._next_id
             self._next_id += 1
         r = Request(rid, camera, klass, time.perf_counter() if arrival is None else arrival, ob)
-        if ob + self.backend.slot_bytes(klass, 1) > self.budget:
+        if ob + self.backend.slot_bytes((klass,)) > self.budget:
             r.error = "request larger than the memory budget"
             r.t_done = time.perf_counter()
             r.done.set()
@@ -148,31 +185,94 @@ class Server:
         if self._thread:
             self._thread.join(timeout)
 
-    def _free(self) -> int:
-        return self.budget - self._used
+    def prewarm(self, combo: Sequence[Klass]) -> bool:
+        """Create an idle slot for a class multiset before serving (e.g. to
+        capture its graph outside the measured trace), if it fits the budget
+        after evicting idle slots; returns whether it was created."""
+        combo = tuple(sorted(tuple(k) for k in combo))
+        with self._lock:
+            if not self._fits(combo, 0) or self._idle(combo):
+                return False
+            s = self._acquire(combo, 0)
+            s.busy = False
+        return True
 
-    def _form_batch(self) -> Optional[List[Request]]:
+    def close(self):
+        """Stop and destroy every cached slot."""
+        self.stop()
+        for s in list(self._slots):
+            self._drop(s)
+
+    @property
+    def used_bytes(self) -> int:
+        return self._slot_mem + self._out_mem
+
+    def _idle(self, combo: Optional[Combo] = None) -> List[_Slot]:
+        return [s for s in self._slots if not s.busy and (combo is None or s.combo == combo)]
+
+    def _cost(self, combo: Combo, outs: int) -> int:
+        """Memory the batch would add: its outputs, plus a new slot unless an
+        idle one of the same multiset exists."""
+        return outs + (0 if self._idle(combo) else self.backend.slot_bytes(combo))
+
+    def _fits(self, combo: Combo, outs: int) -> bool:
+        reuse = bool(self._idle(combo))
+        evictable = sum(s.nbytes for s in self._idle() if not (reuse and s.combo == combo))
+        return self.used_bytes - evictable + self._cost(combo, outs) <= self.budget
+
+    def _form_batch(self) -> Optional[Tuple[List[Request], Combo]]:
         with self._lock:
             if not self._q:
                 return None
             head = self._q[0]
-            klass = head.klass
-            batch = []
+            batch: List[Request] = []
             for r in list(self._q):
-                if r.klass != klass:
-                    continue
                 if len(batch) >= self.max_batch:
                     break
-                need = sum(x.out_bytes for x in batch) + r.out_bytes + \
-                    self.backend.slot_bytes(klass, len(batch) + 1)
-                if need > self._free():
+                if not self.mix_classes and r.klass != head.klass:
+                    continue
+                cand = batch + [r]
+                combo = tuple(sorted(q.klass for q in cand))
+                if not self._fits(combo, sum(q.out_bytes for q in cand)):
                     break
-                batch.append(r)
+                batch = cand
             if not batch:
                 return None
             for r in batch:
                 self._q.remove(r)
-            return batch
+            batch.sort(key=lambda q: (q.klass, q.rid))
+            return batch, tuple(q.klass for q in batch)
+
+    def _drop(self, s: _Slot):
+        self.backend.destroy_slot(s.handle)
+        self._slots.remove(s)
+        self._slot_mem -= s.nbytes
+
+    def _acquire(self, combo: Combo, outs: int) -> _Slot:
+        """An idle slot of `combo` (or a new one), after evicting other idle
+        slots, least recently used first, until the batch's outputs and the
+        new slot fit."""
+        self._tick += 1
+        idle = self._idle(combo)
+        keep = max(idle, key=lambda x: x.last_use) if idle else None
+        need = 0 if keep is not None else self.backend.slot_bytes(combo)
+        for victim in sorted(self._idle(), key=lambda x: x.last_use):
+            if self.used_bytes + need + outs <= self.budget:
+                break
+            if victim is keep:
+                continue
+            self._drop(victim)
+            self.evictions += 1
+        if keep is not None:
+            s = keep
+        else:
+            s = _Slot(combo, self.backend.create_slot(combo), need)
+            self._slots.append(s)
+            self._slot_mem += need
+            self.slots_created += 1
+        s.busy = True
+        s.last_use = self._tick
+        return s
 
     def _loop(self):
         lanes = list(range(self.max_inflight))
@@ -180,7 +280,7 @@ class Server:
             progressed = False
             # completions
             for item in list(self._inflight):
-                bid, h, batch, lane = item
+                bid, h, batch, lane, slot = item
                 if self.backend.poll(h):
                     try:
                         outs = self.backend.finish(h)
@@ -195,43 +295,50 @@ class Server:
                     self.backend.release(h)
                     with self._lock:
                         self._inflight.remove(item)
-                        self._used -= sum(r.out_bytes for r in batch) + \
-                            self.backend.slot_bytes(batch[0].klass, len(batch))
+                        self._out_mem -= sum(r.out_bytes for r in batch)
+                        slot.busy = False
                         self.completed.extend(batch)
                     lanes.append(lane)
                     progressed = True
             # admissions
             while lanes:
-                batch = self._form_batch()
-                if batch is None:
+                formed = self._form_batch()
+                if formed is None:
                     break
-                klass = batch[0].klass
+                batch, combo = formed
                 bid = self._next_batch
                 self._next_batch += 1
-                mem = sum(r.out_bytes for r in batch) + self.backend.slot_bytes(klass, len(batch))
+                outs = sum(r.out_bytes for r in batch)
                 lane = lanes.pop(0)
+                slot = None
                 try:
                     if self.fail_hook is not None and self.fail_hook(bid):
                         raise RuntimeError("injected failure")
-                    h = self.backend.launch(klass, [r.camera for r in batch], lane)
+                    with self._lock:
+                        slot = self._acquire(combo, outs)
+                    h = self.backend.launch(slot.handle, [r.camera for r in batch], lane)
                 except Exception as e:
                     now = time.perf_counter()
                     for r in batch:
                         r.error, r.t_done, r.batch_id = f"render failed: {e}", now, bid
                         r.done.set()
                     with self._lock:
+                        if slot is not None:
+                            slot.busy = False
                         self.completed.extend(batch)
                     lanes.append(lane)
                     continue
                 for r in batch:
                     r.batch_id = bid
                 with self._lock:
-                    self._used += mem
-                    self._peak = max(self._peak, self._used)
-                    self._inflight.append((bid, h, batch, lane))
+                    self._out_mem += outs
+                    self._peak = max(self._peak, self.used_bytes)
+                    self._inflight.append((bid, h, batch, lane, slot))
                     self.peak_inflight = max(self.peak_inflight, len(self._inflight))
                 self.batches += 1
                 self.batch_sizes.append(len(batch))
+                if len(set(combo)) > 1:
+                    self.mixed_batches += 1
                 progressed = True
             if not progressed:
                 time.sleep(self.idle_sleep)
@@ -254,8 +361,11 @@ class Server:
                 "batches": self.batches,
                 "mean_batch": float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0,
                 "max_batch": int(max(self.batch_sizes)) if self.batch_sizes else 0,
+                "mixed_batches": self.mixed_batches,
                 "peak_inflight": int(self.peak_inflight),
-                "peak_mem_bytes": int(self._peak), "per_class": per_class}
+                "slots_created": self.slots_created, "evictions": self.evictions,
+                "peak_mem_bytes": int(self._peak), "budget_bytes": self.budget,
+                "per_class": per_class}
 
 
 def replay(server: Server, trace: Sequence[Tuple[float, Any]], warmup: int = 0):
@@ -281,10 +391,15 @@ def replay(server: Server, trace: Sequence[Tuple[float, Any]], warmup: int = 0):
 # ---------------------------------------------------------------------------
 
 class GpuBackend(Backend):
-    """Fused multi-view forward of a batch of same-size views, replayed from a
-    HIP graph captured per (class, batch size, lane)."""
+    """Fused multi-view forward of a batch, replayed from a HIP graph captured
+    for the batch's multiset of classes (or launched eagerly with
+    use_graphs=False)."""
 
-    def __init__(self, ctx, scene, layers: int = 4, alpha: float = 0.01, use_graphs: bool = True):
+    def __init__(self, ctx, scene, layers: int = 4, alpha: float = 0.01, use_graphs: bool = True,
+                 candidates: bool = True):
+        """candidates: every slot holds a [V, n] byte buffer for the depth
+        pass's candidate layers, so the accumulation skips the points that
+        cannot blend (n bytes per view of slot memory)."""
         import torch
         from . import adop
         self.torch = torch
@@ -294,55 +409,63 @@ class GpuBackend(Backend):
         self.layers = layers
         self.alpha = alpha
         self.use_graphs = use_graphs
+        self.candidates = candidates
         self.C = scene.channels
         self.dev = scene.x.device
         self.streams = {}
-        self.slots: Dict[Tuple[Tuple[int, int], int, int], Any] = {}
 
-    def _pixels(self, klass, b=1):
+    def _pixels(self, klass):
         w, h = klass
-        return b * sum((w >> l) * (h >> l) for l in range(self.layers))
+        return sum((w >> l) * (h >> l) for l in range(self.layers))
 
     def out_bytes(self, klass) -> int:
         return self._pixels(klass) * self.C * 4
 
-    def slot_bytes(self, klass, batch: int) -> int:
-        px = self._pixels(klass, batch)
-        return px * (self.C * 4 + 8 + 4) + self.ctx.workspace_bytes(self.C, batch, px)
+    def slot_bytes(self, combo) -> int:
+        px = sum(self._pixels(k) for k in combo)
+        cand = len(combo) * self.scene.n if self.candidates else 0
+        return px * (self.C * 4 + 8 + 4) + self.ctx.workspace_bytes(self.C, len(combo), px) + cand
 
     def _stream(self, lane):
         if lane not in self.streams:
             self.streams[lane] = self.torch.cuda.Stream(device=self.dev)
         return self.streams[lane]
 
-    def _slot(self, klass, cams, lane):
-        key = (klass, len(cams), lane)
-        s = self.slots.get(key)
-        if s is None:
-            if self.use_graphs:
-                s = self.adop.ForwardGraph(self.ctx, self.scene, cams, self.layers, alpha=self.alpha)
-            else:
-                fr = self.adop.Frame(cams, self.layers, self.C, self.dev)
-                ws = self.torch.empty(self.ctx.workspace_bytes(self.C, len(cams), fr.pixels),
-                                      dtype=self.torch.uint8, device=self.dev)
-                s = (fr, ws)
-            self.slots[key] = s
-        return s
+    def _dummy(self, combo):
+        from . import synth
+        return [synth.Camera(w, h, 0.8 * w, 0.8 * w, w / 2.0, h / 2.0) for (w, h) in combo]
 
-    def launch(self, klass, cams, lane):
+    def create_slot(self, combo):
+        cams = self._dummy(combo)
+        if self.use_graphs:
+            return self.adop.ForwardGraph(self.ctx, self.scene, cams, self.layers, alpha=self.alpha,
+                                          record_visibility=self.candidates)
+        fr = self.adop.Frame(cams, self.layers, self.C, self.dev)
+        if self.candidates:
+            fr.visible = self.torch.empty((len(cams), self.scene.n), dtype=self.torch.uint8, device=self.dev)
+        ws = self.torch.empty(self.ctx.workspace_bytes(self.C, len(cams), fr.pixels),
+                              dtype=self.torch.uint8, device=self.dev)
+        return (fr, ws)
+
+    def destroy_slot(self, slot):
+        if self.use_graphs:
+            slot.close()
+
+    def launch(self, slot, cams, lane):
         torch = self.torch
         st = self._stream(lane)
-        slot = self._slot(klass, cams, lane)
         if self.use_graphs:
             frame = slot.launch(cams, stream=st)
         else:
             fr, ws = slot
             frame = self.adop.render_forward(self.ctx, self.scene, cams, self.layers, alpha=self.alpha,
-                                             frame=fr, workspace=ws, stream=st, record_visibility=False)
+                                             frame=fr, workspace=ws, stream=st,
+                                             record_visibility=self.candidates)
         with torch.cuda.stream(st):
-            outs = [frame.images[self.C * int(frame.offsets[v, 0]):
-                                 self.C * (int(frame.offsets[v, 0]) + self._pixels(klass))].clone()
-                    for v in range(len(cams))]
+            outs = []
+            for v, c in enumerate(cams):
+                o = int(frame.offsets[v, 0])
+                outs.append(frame.images[self.C * o: self.C * (o + self._pixels((c.width, c.height)))].clone())
             ev = torch.cuda.Event()
             ev.record(st)
         return (ev, outs)
@@ -355,7 +478,8 @@ class GpuBackend(Backend):
 
 
 class PlainBackend(GpuBackend):
-    """The unbatched baseline: FP32 scene, eager launches, one view at a time."""
+    """The unbatched baseline: FP32 scene, eager launches of the plain
+    forward (no candidate buffer), one view at a time."""
 
     def __init__(self, ctx, scene, layers: int = 4, alpha: float = 0.01):
-        super().__init__(ctx, scene, layers, alpha, use_graphs=False)
+        super().__init__(ctx, scene, layers, alpha, use_graphs=False, candidates=False)

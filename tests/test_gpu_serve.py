@@ -1,5 +1,6 @@
-"""Serving on the GPU: mixed-resolution requests batched as they arrive give,
-for every request, the same image as that camera rendered alone (floats within
+"""Serving on the GPU: mixed-resolution requests batched as they arrive (fused
+launches that mix resolution classes) give, for every request, the same image
+as that camera rendered alone (floats within
 1e-5 relative: both are FP32 sums, in different orders), and a sample matches
 the CPU oracle."""
 import numpy as np
@@ -35,12 +36,13 @@ def test_served_equals_alone(oracle, graphs):
     assert st["completed"] == len(burst) and st["failed"] == 0
     assert st["max_batch"] > 1, "no batch held more than one view"
     assert st["peak_inflight"] > 1, "batches never overlapped on the GPU"
+    assert st["mixed_batches"] > 0, "no batch mixed resolution classes"
     mixed = [r for r in burst if sum(q.batch_id == r.batch_id for q in burst) > 1]
     assert len(mixed) >= 4
     # then a Poisson trace while the server runs
     tr = synth.config5_requests(48, rate=400.0, seed=77)
     reqs = burst + serve.replay(srv, tr)
-    srv.stop()
+    srv.close()
     st = srv.stats()
     print(st)
     assert st["completed"] == len(reqs) and st["failed"] == 0
