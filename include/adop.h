@@ -95,6 +95,7 @@ typedef int32_t adop_dtype;
  * ties to even (Eq. round).  A point is culled when Z <= znear, when
  * r2 > r2_max (distortion fold-over limit), or when anything is non-finite.
  * Requirements: width, height >= 1; znear >= 0.  100 bytes. */
+struct adop_camera;
 typedef struct adop_camera {
     int32_t width, height;
     float fx, fy, cx, cy;
@@ -111,6 +112,13 @@ typedef struct adop_render_params {
     uint32_t flags;            /* ADOP_FLAG_* */
     const float* background;   /* host, [channels] colour of empty pixels; NULL = zeros */
     float gamma;               /* ADOP_FLAG_DISCARD: > 0 (the paper uses 1.5) */
+    /* Optional device camera table of the V views (adop_cameras_upload, or
+     * written by device code): when not NULL the render call reads each
+     * view's intrinsics (fx .. p2), znear, r2_max and pose (R, t) from it on
+     * the device when the call executes; the host array `cams` of the call
+     * then only supplies the image sizes (which must match the table's) and
+     * its other fields are validated but not used.  NULL: the host cameras. */
+    const struct adop_camera* cameras_device;
 } adop_render_params;
 
 /* A prepared scene (see adop_scene_prepare).  The SoA position planes and the
@@ -177,6 +185,47 @@ size_t adop_workspace_bytes(const adop_context* ctx, int32_t channels, int32_t V
 
 /* Bytes of the prepared feature array for n points, C channels, dtype. */
 size_t adop_feature_bytes(int64_t n, int32_t channels, adop_dtype dtype);
+
+/* Layout of one view's pyramid (Eq. 2: layer l is (w >> l) x (h >> l)) in the
+ * frame buffers, for w x h pixels, L layers and C channels: layer sizes, the
+ * first pixel of each layer in keys and counts (pixel_offset; images hold
+ * C * pixel_offset floats before the layer), and the bytes of the view's
+ * images (FP32), keys (u64) and counts (int32).  Host only; ADOP_E_INVALID
+ * when w >> (L-1) or h >> (L-1) is 0 or L is outside 1..ADOP_MAX_LAYERS. */
+typedef struct adop_layout {
+    int32_t layers, channels;
+    int32_t width[ADOP_MAX_LAYERS];
+    int32_t height[ADOP_MAX_LAYERS];
+    int64_t pixel_offset[ADOP_MAX_LAYERS];
+    int64_t pixels;            /* sum of the layers' pixels */
+    int64_t image_bytes;       /* C * pixels * 4 */
+    int64_t key_bytes;         /* pixels * 8 */
+    int64_t count_bytes;       /* pixels * 4 */
+} adop_layout;
+adop_status adop_pyramid_layout(int32_t width, int32_t height, int32_t layers, int32_t channels,
+                                adop_layout* out);
+
+/* A prepared scene in ONE caller-owned device buffer: the planes x, y, z
+ * (FP32 [n] each), the features [n][C] of dtype and orig_index (int32 [n]),
+ * in this order, each part starting on a 256-byte boundary.
+ * adop_scene_bytes gives the buffer size (0 for invalid arguments);
+ * adop_scene_bind fills `out` with pointers into `scene_mem` (which must be
+ * 256-byte aligned; nothing is read or copied, so it needs no context and
+ * no device), sets n, channels and dtype, and leaves the optional per-point
+ * planes (normals, radius, beta) NULL.  adop_scene_prepare can then write
+ * the prepared points through those pointers. */
+size_t adop_scene_bytes(int64_t n, int32_t channels, adop_dtype dtype);
+adop_status adop_scene_bind(void* scene_mem, int64_t n, int32_t channels, adop_dtype dtype,
+                            adop_scene* out);
+
+/* Copy V host cameras into a device camera table (caller-owned device memory
+ * of V * sizeof(adop_camera) bytes, 4-byte aligned) for
+ * adop_render_params.cameras_device.  The cameras are validated like those of
+ * a render call (sizes, znear >= 0) and staged through a pinned slot of the
+ * context, so `host` may be reused as soon as the call returns; the copy is
+ * asynchronous on `stream`. */
+adop_status adop_cameras_upload(adop_context* ctx, const adop_camera* host, int32_t V,
+                                adop_camera* dev_table, void* stream);
 
 /* ------------------------------------------------------- scene upload */
 /* Reorder a point cloud for rendering (Sec. 3.1, "Implementation Details":

@@ -46,7 +46,17 @@ class Camera(ct.Structure):
 
 class RenderParams(ct.Structure):
     _fields_ = [("layers", ct.c_int32), ("alpha", ct.c_float), ("flags", ct.c_uint32),
-                ("background", ct.c_void_p), ("gamma", ct.c_float)]
+                ("background", ct.c_void_p), ("gamma", ct.c_float), ("cameras_device", ct.c_void_p)]
+
+
+MAX_LAYERS_ = 8
+
+
+class Layout(ct.Structure):
+    _fields_ = [("layers", ct.c_int32), ("channels", ct.c_int32),
+                ("width", ct.c_int32 * MAX_LAYERS_), ("height", ct.c_int32 * MAX_LAYERS_),
+                ("pixel_offset", ct.c_int64 * MAX_LAYERS_), ("pixels", ct.c_int64),
+                ("image_bytes", ct.c_int64), ("key_bytes", ct.c_int64), ("count_bytes", ct.c_int64)]
 
 
 class SceneDesc(ct.Structure):
@@ -89,6 +99,14 @@ def lib():
         L.adop_workspace_bytes.argtypes = [P, I32, I32, I64]
         L.adop_feature_bytes.restype = ct.c_size_t
         L.adop_feature_bytes.argtypes = [I64, I32, I32]
+        L.adop_pyramid_layout.restype = S
+        L.adop_pyramid_layout.argtypes = [I32, I32, I32, I32, P]
+        L.adop_scene_bytes.restype = ct.c_size_t
+        L.adop_scene_bytes.argtypes = [I64, I32, I32]
+        L.adop_scene_bind.restype = S
+        L.adop_scene_bind.argtypes = [P, I64, I32, I32, P]
+        L.adop_cameras_upload.restype = S
+        L.adop_cameras_upload.argtypes = [P, P, I32, P, P]
         L.adop_scene_prepare.restype = S
         L.adop_scene_prepare.argtypes = [P, P, P, I64, I32, I32, I32, ct.c_uint64, P, P, P, P, P, P]
         L.adop_scene_gather.restype = S
@@ -119,6 +137,7 @@ def lib():
 
 EXPORTS = ["adop_version", "adop_status_string", "adop_context_create", "adop_context_destroy",
            "adop_last_error", "adop_views_layout", "adop_workspace_bytes", "adop_feature_bytes",
+           "adop_pyramid_layout", "adop_scene_bytes", "adop_scene_bind", "adop_cameras_upload",
            "adop_scene_prepare", "adop_scene_gather", "adop_knn_radius",
            "adop_render_forward", "adop_render_forward_noalloc", "adop_render_backward",
            "adop_forward_graph_create", "adop_forward_graph_launch", "adop_graph_destroy",
@@ -167,6 +186,32 @@ def views_layout(cams, layers: int):
     if st != OK:
         raise AdopError(st, "invalid cameras/layers")
     return int(total.value), offs
+
+
+def pyramid_layout(width: int, height: int, layers: int, channels: int) -> dict:
+    """adop_pyramid_layout as a dict (host only)."""
+    out = Layout()
+    st = lib().adop_pyramid_layout(width, height, layers, channels, ct.byref(out))
+    if st != OK:
+        raise AdopError(st, "invalid pyramid")
+    return {"layers": out.layers, "channels": out.channels,
+            "width": list(out.width[:layers]), "height": list(out.height[:layers]),
+            "pixel_offset": list(out.pixel_offset[:layers]), "pixels": out.pixels,
+            "image_bytes": out.image_bytes, "key_bytes": out.key_bytes, "count_bytes": out.count_bytes}
+
+
+CAMERA_FLOATS = 25   # sizeof(adop_camera) / 4
+
+
+def cameras_upload(ctx: "Context", cams, stream=None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Device camera table [V, 25] (the adop_camera records as 4-byte words)."""
+    arr = cams if isinstance(cams, ct.Array) else make_cameras(cams)
+    V = len(arr)
+    if out is None:
+        out = torch.empty((V, CAMERA_FLOATS), dtype=torch.float32, device=f"cuda:{ctx.device}")
+    assert out.is_cuda and out.is_contiguous() and out.numel() == V * CAMERA_FLOATS
+    ctx.check(lib().adop_cameras_upload(ctx.handle, arr, V, _ptr(out), _stream(stream)), "adop_cameras_upload")
+    return out
 
 
 class Context:
@@ -312,12 +357,16 @@ FLAG_DISCARD = 16
 GAMMA = 1.5   # the paper's discarding parameter
 
 
-def _params(layers: int, alpha: float, flags: int, background, C: int, gamma: float = GAMMA):
+def _params(layers: int, alpha: float, flags: int, background, C: int, gamma: float = GAMMA,
+            cams_device: Optional[torch.Tensor] = None, V: int = 0):
     bg = None
     if background is not None:
         bg = (ct.c_float * C)(*[float(b) for b in np.asarray(background, np.float32).reshape(C)])
+    if cams_device is not None:
+        assert cams_device.is_cuda and cams_device.is_contiguous() and cams_device.dtype == torch.float32
+        assert cams_device.numel() == V * CAMERA_FLOATS, "camera table must hold the views' cameras"
     p = RenderParams(layers, float(np.float32(alpha)), flags, ct.cast(bg, ct.c_void_p) if bg is not None else None,
-                     float(np.float32(gamma)))
+                     float(np.float32(gamma)), _ptr(cams_device))
     return p, bg
 
 
@@ -360,10 +409,12 @@ class Frame:
 def render_forward(ctx: Context, scene: Scene, cams, layers: int, alpha: float = 0.01, flags: int = 0,
                    background=None, frame: Optional[Frame] = None, stream=None,
                    workspace: Optional[torch.Tensor] = None, gamma: float = GAMMA,
-                   record_visibility: bool = True) -> Frame:
+                   record_visibility: bool = True, cams_device: Optional[torch.Tensor] = None) -> Frame:
     """record_visibility: also write frame.visible ([V, n] uint8, bit l =
     the point is in layer l's blend set), which lets render_backward skip
-    the points that blend nowhere; False leaves frame.visible unset."""
+    the points that blend nowhere; False leaves frame.visible unset.
+    cams_device: a device camera table ([V, 25], cameras_upload) whose
+    intrinsics and poses replace those of `cams` (which give the sizes)."""
     C = scene.channels
     if frame is None:
         frame = Frame(cams, layers, C, scene.x.device)
@@ -381,7 +432,7 @@ def render_forward(ctx: Context, scene: Scene, cams, layers: int, alpha: float =
             frame.visible = torch.empty(shape, dtype=torch.uint8, device=scene.x.device)
     else:
         frame.visible = None
-    p, keep = _params(layers, alpha, flags, background, C, gamma)
+    p, keep = _params(layers, alpha, flags, background, C, gamma, cams_device, len(frame.cams))
     sd = scene.desc()
     fd = frame.desc()
     st = lib().adop_render_forward(ctx.handle, ct.byref(sd), frame.cams, len(frame.cams), ct.byref(p),
@@ -414,8 +465,10 @@ def render_forward_noalloc(ctx: Context, scene: Scene, frame: Frame, alpha: floa
 
 def render_backward(ctx: Context, scene: Scene, frame: Frame, grad: torch.Tensor, alpha: float = 0.01,
                     flags: int = 0, background=None, stream=None, out=None,
-                    workspace: Optional[torch.Tensor] = None, gamma: float = GAMMA):
-    """Returns (dfeat [n,C] f32, dpos [3,n] f32, dpose [V,6] f64, dintr [V,9] f64)."""
+                    workspace: Optional[torch.Tensor] = None, gamma: float = GAMMA,
+                    cams_device: Optional[torch.Tensor] = None):
+    """Returns (dfeat [n,C] f32, dpos [3,n] f32, dpose [V,6] f64, dintr [V,9] f64).
+    cams_device: the camera table the forward of this frame used, if any."""
     C = scene.channels
     V = len(frame.cams)
     dev = scene.x.device
@@ -430,7 +483,7 @@ def render_backward(ctx: Context, scene: Scene, frame: Frame, grad: torch.Tensor
     if frame.visible is not None and tuple(frame.visible.shape) != (V, scene.n):
         raise ValueError("frame.visible was recorded for another scene")
     ws = workspace if workspace is not None else ctx.workspace(C, V, frame.pixels)
-    p, keep = _params(frame.layers, alpha, flags, background, C, gamma)
+    p, keep = _params(frame.layers, alpha, flags, background, C, gamma, cams_device, V)
     sd = scene.desc()
     fd = frame.desc()
     st = lib().adop_render_backward(ctx.handle, ct.byref(sd), frame.cams, V, ct.byref(p), ct.byref(fd),

@@ -261,6 +261,33 @@ adop_status stage_views(adop_context* ctx, const adop_camera* cams, int32_t V, i
     return ADOP_OK;
 }
 
+// Intrinsics, near plane, fold-over limit and pose of V views from a device
+// camera table into the staged view records (sizes and the layer table stay
+// those of the host cameras).
+__global__ void k_views_from_table(const adop_camera* __restrict__ cams, int V, ViewRec* __restrict__ views) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const adop_camera c = cams[v];
+    ViewRec& r = views[v];
+    r.fx = c.fx; r.fy = c.fy; r.cx = c.cx; r.cy = c.cy;
+    r.k1 = c.k1; r.k2 = c.k2; r.k3 = c.k3; r.p1 = c.p1; r.p2 = c.p2;
+    r.znear = c.znear; r.r2max = c.r2_max;
+    for (int k = 0; k < 9; ++k) r.R[k] = c.R[k];
+    for (int k = 0; k < 3; ++k) r.t[k] = c.t[k];
+}
+
+// Stage the host cameras' view records, then (with a device camera table)
+// overwrite their camera fields on the device.
+adop_status stage_cameras(adop_context* ctx, const adop_camera* cams, int32_t V, const adop_render_params* params,
+                          void* ws, hipStream_t st) {
+    adop_status s = stage_views(ctx, cams, V, params->layers, ws, st);
+    if (s || !params->cameras_device) return s;
+    k_views_from_table<<<(V + 63) / 64, 64, 0, st>>>(params->cameras_device, V, static_cast<ViewRec*>(ws));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e, "camera table");
+    return ADOP_OK;
+}
+
 hipEvent_t take_event(adop_context* ctx) {
     if (!ctx->pool.empty()) {
         hipEvent_t e = ctx->pool.back();
@@ -457,6 +484,81 @@ size_t adop_feature_bytes(int64_t n, int32_t channels, adop_dtype dtype) {
     return (size_t)n * channels * (dtype == ADOP_F32 ? 4 : 2);
 }
 
+adop_status adop_pyramid_layout(int32_t width, int32_t height, int32_t layers, int32_t channels, adop_layout* out) {
+    if (!out) return ADOP_E_INVALID;
+    std::memset(out, 0, sizeof *out);
+    if (layers < 1 || layers > ADOP_MAX_LAYERS || channels < 1 || channels > ADOP_MAX_CHANNELS || width < 1 ||
+        height < 1 || (width >> (layers - 1)) < 1 || (height >> (layers - 1)) < 1)
+        return ADOP_E_INVALID;
+    out->layers = layers;
+    out->channels = channels;
+    int64_t acc = 0;
+    for (int l = 0; l < layers; ++l) {
+        out->width[l] = width >> l;
+        out->height[l] = height >> l;
+        out->pixel_offset[l] = acc;
+        acc += (int64_t)out->width[l] * out->height[l];
+    }
+    out->pixels = acc;
+    out->image_bytes = acc * channels * 4;
+    out->key_bytes = acc * 8;
+    out->count_bytes = acc * 4;
+    return ADOP_OK;
+}
+
+size_t adop_scene_bytes(int64_t n, int32_t channels, adop_dtype dtype) {
+    if (n < 0 || n > 0x7fffffffLL || channels < 1 || channels > ADOP_MAX_CHANNELS || dtype < ADOP_F32 ||
+        dtype > ADOP_F16)
+        return 0;
+    const size_t plane = align256((size_t)n * sizeof(float));
+    const size_t fb = align256((size_t)n * channels * (dtype == ADOP_F32 ? 4 : 2));
+    return 3 * plane + fb + align256((size_t)n * sizeof(int32_t));
+}
+
+adop_status adop_scene_bind(void* scene_mem, int64_t n, int32_t channels, adop_dtype dtype, adop_scene* out) {
+    if (!out) return ADOP_E_INVALID;
+    std::memset(out, 0, sizeof *out);
+    if (adop_scene_bytes(n, channels, dtype) == 0) return ADOP_E_INVALID;
+    if (!scene_mem || ((uintptr_t)scene_mem & 255) != 0) return ADOP_E_INVALID;
+    unsigned char* p = static_cast<unsigned char*>(scene_mem);
+    const size_t plane = align256((size_t)n * sizeof(float));
+    const size_t fb = align256((size_t)n * channels * (dtype == ADOP_F32 ? 4 : 2));
+    out->n = n;
+    out->channels = channels;
+    out->dtype = dtype;
+    out->x = reinterpret_cast<const float*>(p);
+    out->y = reinterpret_cast<const float*>(p + plane);
+    out->z = reinterpret_cast<const float*>(p + 2 * plane);
+    out->feat = p + 3 * plane;
+    out->orig_index = reinterpret_cast<const int32_t*>(p + 3 * plane + fb);
+    return ADOP_OK;
+}
+
+adop_status adop_cameras_upload(adop_context* ctx, const adop_camera* host, int32_t V, adop_camera* dev_table,
+                                void* stream) {
+    if (!ctx) return ADOP_E_INVALID;
+    ctx->err.clear();
+    adop_status s = check_cameras(ctx, host, V, 1, ADOP_MAX_VIEWS);
+    if (s) return s;
+    if (!dev_table || ((uintptr_t)dev_table & 3) != 0)
+        return fail(ctx, ADOP_E_INVALID, "dev_table must be a 4-byte aligned device pointer");
+    int slot = ctx->next;
+    ctx->next = (ctx->next + 1) % kSlots;
+    hipError_t e;
+    if (ctx->used[slot] && (e = hipEventSynchronize(ctx->ev[slot])) != hipSuccess)
+        return hip_fail(ctx, e, "hipEventSynchronize");
+    unsigned char* staging = ctx->pinned + (size_t)slot * kSlotBytes;
+    static_assert((size_t)ADOP_MAX_VIEWS * sizeof(adop_camera) <= kSlotBytes, "staging slot");
+    std::memcpy(staging, host, (size_t)V * sizeof(adop_camera));
+    hipStream_t st = (hipStream_t)stream;
+    if ((e = hipMemcpyAsync(dev_table, staging, (size_t)V * sizeof(adop_camera), hipMemcpyHostToDevice, st)) !=
+        hipSuccess)
+        return hip_fail(ctx, e, "hipMemcpyAsync(cameras)");
+    if ((e = hipEventRecord(ctx->ev[slot], st)) != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
+    ctx->used[slot] = true;
+    return ADOP_OK;
+}
+
 adop_status adop_scene_prepare(adop_context* ctx, const float* pos, const void* feat, int64_t n, int32_t channels,
                                adop_dtype dtype, int32_t block, uint64_t seed, float* x, float* y, float* z,
                                void* feat_out, int32_t* orig_index, void* stream) {
@@ -507,7 +609,7 @@ adop_status adop_render_forward(adop_context* ctx, const adop_scene* scene, cons
     adop_status s = check_common(ctx, scene, cams, V, params, frame, workspace, workspace_bytes_, ADOP_MAX_VIEWS, &total);
     if (s) return s;
     hipStream_t st = (hipStream_t)stream;
-    s = stage_views(ctx, cams, V, params->layers, workspace, st);
+    s = stage_cameras(ctx, cams, V, params, workspace, st);
     if (s) return s;
     adop::FwdArgs a = fwd_args(ctx, scene, cams, V, params, frame, workspace, total);
     hipError_t e = adop::launch_forward(a, st);
@@ -544,7 +646,7 @@ adop_status adop_render_forward_noalloc(adop_context* ctx, const adop_scene* sce
     adop_status s = check_common(ctx, scene, cams, V, params, frame, ctx->scratch_dev, ADOP_NOALLOC_SCRATCH_BYTES,
                                  ADOP_MAX_VIEWS, &total, true);
     if (s) return s;
-    s = stage_views(ctx, cams, V, params->layers, ctx->scratch_dev, st);
+    s = stage_cameras(ctx, cams, V, params, ctx->scratch_dev, st);
     if (s) return s;
     adop::FwdArgs a = fwd_args(ctx, scene, cams, V, params, frame, ctx->scratch_dev, total);
     e = adop::launch_forward(a, st);
@@ -564,7 +666,7 @@ adop_status adop_render_backward(adop_context* ctx, const adop_scene* scene, con
     if (scene->n > 0 && (!dfeat || !dpos)) return fail(ctx, ADOP_E_INVALID, "NULL dfeat/dpos");
     if (scene->n > 0 && ((uintptr_t)dfeat & 15) != 0) return fail(ctx, ADOP_E_INVALID, "dfeat must be 16-byte aligned");
     hipStream_t st = (hipStream_t)stream;
-    s = stage_views(ctx, cams, V, params->layers, workspace, st);
+    s = stage_cameras(ctx, cams, V, params, workspace, st);
     if (s) return s;
     adop::BwdArgs a;
     a.dtype = scene->dtype;
@@ -637,7 +739,12 @@ adop_status adop_forward_graph_create(adop_context* ctx, const adop_scene* scene
     a.timer = adop::Timer();
     if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess)
         return cleanup(hip_fail(ctx, e, "hipStreamBeginCapture"));
-    hipError_t le = adop::launch_forward(a, cs);
+    hipError_t le = hipSuccess;
+    if (params->cameras_device) {
+        k_views_from_table<<<(V + 63) / 64, 64, 0, cs>>>(params->cameras_device, V, g->views_dev);
+        le = hipGetLastError();
+    }
+    if (le == hipSuccess) le = adop::launch_forward(a, cs);
     e = hipStreamEndCapture(cs, &g->graph);
     if (le != hipSuccess) return cleanup(hip_fail(ctx, le, "forward launch (capture)"));
     if (e != hipSuccess) return cleanup(hip_fail(ctx, e, "hipStreamEndCapture"));

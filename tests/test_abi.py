@@ -80,3 +80,40 @@ def test_workspace_bytes(A):
     assert L.adop_workspace_bytes(None, 17, 1, 10) == 0
     assert L.adop_feature_bytes(10, 4, A.BF16) == 80
     assert L.adop_feature_bytes(10, 4, A.F32) == 160
+
+
+def test_pyramid_layout(A):
+    lay = A.pyramid_layout(1920, 1080, 5, 4)
+    assert lay["width"] == [1920, 960, 480, 240, 120] and lay["height"] == [1080, 540, 270, 135, 67]
+    total, offs = A.views_layout([_cam(1920, 1080)], 5)
+    assert lay["pixels"] == total == 2_762_040
+    assert lay["pixel_offset"] == list(offs[0])
+    assert lay["image_bytes"] == 4 * 4 * total and lay["key_bytes"] == 8 * total and lay["count_bytes"] == 4 * total
+    for w, h, L, C in [(1, 5, 2, 4), (8, 8, 9, 1), (16, 16, 2, 0), (16, 16, 2, 17)]:
+        with pytest.raises(A.AdopError):
+            A.pyramid_layout(w, h, L, C)
+
+
+def test_scene_bind_layout(A):
+    """The single-buffer scene: parts in order x, y, z, feat, orig_index, each
+    on a 256-byte boundary inside adop_scene_bytes; binding reads nothing."""
+    L = A.lib()
+    for n, C, dt in [(1, 1, A.F32), (1000, 4, A.F32), (1000, 3, A.BF16), (12345, 8, A.F16)]:
+        nb = L.adop_scene_bytes(n, C, dt)
+        base = 1 << 40                      # a 256-aligned address that is never dereferenced
+        d = A.SceneDesc()
+        assert L.adop_scene_bind(ct.c_void_p(base), n, C, dt, ct.byref(d)) == A.OK
+        s = 4 if dt == A.F32 else 2
+        ptrs = [d.x, d.y, d.z, d.feat, d.orig_index]
+        sizes = [4 * n, 4 * n, 4 * n, s * C * n, 4 * n]
+        assert ptrs[0] == base and all(p % 256 == 0 for p in ptrs)
+        for k in range(4):
+            assert ptrs[k + 1] >= ptrs[k] + sizes[k]
+            assert ptrs[k + 1] - (ptrs[k] + sizes[k]) < 256
+        assert ptrs[4] + sizes[4] <= base + nb
+        assert (d.n, d.channels, d.dtype) == (n, C, dt)
+        assert not d.nx and not d.radius and not d.beta
+    d = A.SceneDesc()
+    assert L.adop_scene_bind(ct.c_void_p((1 << 40) + 16), 10, 4, A.F32, ct.byref(d)) == A.E_INVALID
+    assert L.adop_scene_bind(ct.c_void_p(1 << 40), 10, 0, A.F32, ct.byref(d)) == A.E_INVALID
+    assert L.adop_scene_bytes(-1, 4, A.F32) == 0 and L.adop_scene_bytes(10, 4, 7) == 0
