@@ -321,6 +321,49 @@ adop_status adop_render_backward(adop_context* ctx, const adop_scene* scene,
                                  float* dfeat, float* dpos, double* dpose, double* dintr,
                                  void* workspace, size_t workspace_bytes, void* stream);
 
+/* ------------------------------------------- photometric tone mapper */
+/* Differentiable tone mapping of Sec. 3.3 for V 3-channel HDR images
+ * [V][3][h][w] FP32 (device), per image i and pixel (u, v):
+ *   I_e = I_hdr * 2^-EV_i                          exposure
+ *   I_w[c] = I_e[c] * white_i[c]                   white point (multiplies)
+ *   I_v = I_w * (1 + a2 r^2 + a4 r^4 + a6 r^6)     vignette, r = |p - c_v|,
+ *       p = ((u + 0.5) / w, (v + 0.5) / h) and c_v = (cx, cy) in the same
+ *       normalised coordinates (pixel centres at integer u, v)
+ *   I_ldr[c] = R_t(I_v[c])                          response (Eq. resonseleak)
+ * R on [0, 1] is a table of K entries per channel sampled at k / (K - 1)
+ * and linearly interpolated (the paper's 1D texture, initialised to x^0.45);
+ * R_t(x) = leak x for x < 0 and -leak / sqrt(x) + leak + 1 for x > 1
+ * (training; the paper uses leak = 0.01); leak < 0 clamps x to [0, 1]
+ * (inference).  Every parameter is a device array, so a training loop can
+ * update them without host round trips. */
+typedef struct adop_tonemap {
+    const float* ev;           /* device [V] exposure values EV_i */
+    const float* white;        /* device [V][3] white points */
+    const float* vignette;     /* device [5]: a2, a4, a6, cx, cy */
+    const float* crf;          /* device [3][K] response tables */
+    int32_t crf_size;          /* K, 2..1024 */
+    float leak;                /* >= 0: leaky response; < 0: clamp */
+} adop_tonemap;
+
+/* ldr [V][3][h][w] FP32 (device); asynchronous on `stream`. */
+adop_status adop_tonemap_forward(adop_context* ctx, const float* hdr, int32_t V, int32_t width,
+                                 int32_t height, const adop_tonemap* tm, float* ldr, void* stream);
+
+/* Workspace bytes of adop_tonemap_backward for V images. */
+size_t adop_tonemap_workspace_bytes(int32_t V);
+
+/* Gradients of L given grad_ldr = dL/dI_ldr [V][3][h][w] FP32 (device
+ * outputs, overwritten): grad_hdr [V][3][h][w] FP32, d_ev [V], d_white [V][3]
+ * (the paper keeps the green entry constant: the caller ignores it),
+ * d_vignette [5] (summed over the V images, which share the camera) and
+ * d_crf [3][K] FP64.  The exposure, white-point and vignette sums are FP64
+ * in a fixed order; the table sums are FP64 in an order that varies between
+ * runs.  Asynchronous on `stream`. */
+adop_status adop_tonemap_backward(adop_context* ctx, const float* hdr, int32_t V, int32_t width,
+                                  int32_t height, const adop_tonemap* tm, const float* grad_ldr,
+                                  float* grad_hdr, double* d_ev, double* d_white, double* d_vignette,
+                                  double* d_crf, void* workspace, size_t workspace_bytes, void* stream);
+
 /* ------------------------------------------------ per-kernel timing */
 /* When enabled, every kernel a render call enqueues is bracketed by HIP
  * events recorded on the same stream.  adop_timing_read waits for the

@@ -107,6 +107,12 @@ def lib():
         L.adop_scene_bind.argtypes = [P, I64, I32, I32, P]
         L.adop_cameras_upload.restype = S
         L.adop_cameras_upload.argtypes = [P, P, I32, P, P]
+        L.adop_tonemap_forward.restype = S
+        L.adop_tonemap_forward.argtypes = [P, P, I32, I32, I32, P, P, P]
+        L.adop_tonemap_workspace_bytes.restype = ct.c_size_t
+        L.adop_tonemap_workspace_bytes.argtypes = [I32]
+        L.adop_tonemap_backward.restype = S
+        L.adop_tonemap_backward.argtypes = [P, P, I32, I32, I32, P, P, P, P, P, P, P, P, ct.c_size_t, P]
         L.adop_scene_prepare.restype = S
         L.adop_scene_prepare.argtypes = [P, P, P, I64, I32, I32, I32, ct.c_uint64, P, P, P, P, P, P]
         L.adop_scene_gather.restype = S
@@ -138,6 +144,7 @@ def lib():
 EXPORTS = ["adop_version", "adop_status_string", "adop_context_create", "adop_context_destroy",
            "adop_last_error", "adop_views_layout", "adop_workspace_bytes", "adop_feature_bytes",
            "adop_pyramid_layout", "adop_scene_bytes", "adop_scene_bind", "adop_cameras_upload",
+           "adop_tonemap_forward", "adop_tonemap_workspace_bytes", "adop_tonemap_backward",
            "adop_scene_prepare", "adop_scene_gather", "adop_knn_radius",
            "adop_render_forward", "adop_render_forward_noalloc", "adop_render_backward",
            "adop_forward_graph_create", "adop_forward_graph_launch", "adop_graph_destroy",
@@ -537,3 +544,61 @@ class ForwardGraph:
 
     def __del__(self):
         self.close()
+
+
+# ---------------------------------------------------------------------------
+# photometric tone mapper
+# ---------------------------------------------------------------------------
+
+class TonemapDesc(ct.Structure):
+    _fields_ = [("ev", ct.c_void_p), ("white", ct.c_void_p), ("vignette", ct.c_void_p), ("crf", ct.c_void_p),
+                ("crf_size", ct.c_int32), ("leak", ct.c_float)]
+
+
+class Tonemapper:
+    """Parameters of the tone mapper as device FP32 tensors: ev [V],
+    white [V, 3], vignette [5] = (a2, a4, a6, cx, cy), crf [3, K]."""
+
+    def __init__(self, ev: torch.Tensor, white: torch.Tensor, vignette: torch.Tensor, crf: torch.Tensor,
+                 leak: float = 0.01):
+        for t in (ev, white, vignette, crf):
+            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+        self.ev, self.white, self.vignette, self.crf, self.leak = ev, white, vignette, crf, leak
+
+    def desc(self) -> TonemapDesc:
+        return TonemapDesc(_ptr(self.ev), _ptr(self.white), _ptr(self.vignette), _ptr(self.crf),
+                           int(self.crf.shape[1]), float(np.float32(self.leak)))
+
+
+def tonemap_forward(ctx: Context, hdr: torch.Tensor, tm: Tonemapper, stream=None) -> torch.Tensor:
+    """hdr [V, 3, h, w] FP32 device -> ldr of the same shape."""
+    assert hdr.is_cuda and hdr.dtype == torch.float32 and hdr.dim() == 4 and hdr.shape[1] == 3
+    hdr = hdr.contiguous()
+    V, _, h, w = hdr.shape
+    out = torch.empty_like(hdr)
+    d = tm.desc()
+    ctx.check(lib().adop_tonemap_forward(ctx.handle, _ptr(hdr), V, w, h, ct.byref(d), _ptr(out), _stream(stream)),
+              "adop_tonemap_forward")
+    return out
+
+
+def tonemap_backward(ctx: Context, hdr: torch.Tensor, tm: Tonemapper, grad: torch.Tensor, stream=None):
+    """(d_hdr [V,3,h,w] f32, d_ev [V], d_white [V,3], d_vignette [5], d_crf [3,K]) (f64)."""
+    hdr = hdr.contiguous()
+    grad = grad.contiguous()
+    V, _, h, w = hdr.shape
+    dev = hdr.device
+    K = int(tm.crf.shape[1])
+    d_hdr = torch.empty_like(hdr)
+    d_ev = torch.empty(V, dtype=torch.float64, device=dev)
+    d_white = torch.empty((V, 3), dtype=torch.float64, device=dev)
+    d_vig = torch.empty(5, dtype=torch.float64, device=dev)
+    d_crf = torch.empty((3, K), dtype=torch.float64, device=dev)
+    nb = int(lib().adop_tonemap_workspace_bytes(V))
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    d = tm.desc()
+    st = lib().adop_tonemap_backward(ctx.handle, _ptr(hdr), V, w, h, ct.byref(d), _ptr(grad), _ptr(d_hdr),
+                                     _ptr(d_ev), _ptr(d_white), _ptr(d_vig), _ptr(d_crf), _ptr(ws), nb,
+                                     _stream(stream))
+    ctx.check(st, "adop_tonemap_backward")
+    return d_hdr, d_ev, d_white, d_vig, d_crf

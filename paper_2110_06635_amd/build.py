@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libadop.so")
 ARCH = os.environ.get("ADOP_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["api.cpp", "render.hip", "render_c1.hip", "render_c2.hip", "render_c3.hip", "render_c4.hip",
-           "scene.hip", "knn.hip"]
+           "scene.hip", "knn.hip", "tonemap.hip"]
 
 COMMON = [
     "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",

@@ -559,6 +559,62 @@ adop_status adop_cameras_upload(adop_context* ctx, const adop_camera* host, int3
     return ADOP_OK;
 }
 
+size_t adop_tonemap_workspace_bytes(int32_t V) {
+    if (V < 1 || V > ADOP_MAX_VIEWS) return 0;
+    return (size_t)V * adop::kTonemapBlocks * 16 * sizeof(double);
+}
+
+static adop_status check_tonemap(adop_context* ctx, const float* hdr, int32_t V, int32_t w, int32_t h,
+                                 const adop_tonemap* tm, adop::TonemapArgs* a) {
+    if (!ctx) return ADOP_E_INVALID;
+    ctx->err.clear();
+    if (V < 1 || V > ADOP_MAX_VIEWS) return fail(ctx, ADOP_E_INVALID, "V=%d outside [1,%d]", V, ADOP_MAX_VIEWS);
+    if (w < 1 || h < 1 || (int64_t)w * h >= ((int64_t)1 << 31))
+        return fail(ctx, ADOP_E_INVALID, "image size %dx%d", w, h);
+    if (!hdr || !tm || !tm->ev || !tm->white || !tm->vignette || !tm->crf)
+        return fail(ctx, ADOP_E_INVALID, "NULL pointer");
+    if (tm->crf_size < 2 || tm->crf_size > adop::kTonemapMaxTable)
+        return fail(ctx, ADOP_E_INVALID, "crf_size=%d outside [2,%d]", tm->crf_size, adop::kTonemapMaxTable);
+    if (!std::isfinite(tm->leak)) return fail(ctx, ADOP_E_INVALID, "leak must be finite");
+    std::memset(a, 0, sizeof *a);
+    a->V = V; a->w = w; a->h = h; a->K = tm->crf_size; a->leak = tm->leak;
+    a->hdr = hdr; a->ev = tm->ev; a->white = tm->white; a->vig = tm->vignette; a->crf = tm->crf;
+    return ADOP_OK;
+}
+
+adop_status adop_tonemap_forward(adop_context* ctx, const float* hdr, int32_t V, int32_t width, int32_t height,
+                                 const adop_tonemap* tm, float* ldr, void* stream) {
+    adop::TonemapArgs a;
+    adop_status s = check_tonemap(ctx, hdr, V, width, height, tm, &a);
+    if (s) return s;
+    if (!ldr) return fail(ctx, ADOP_E_INVALID, "ldr is NULL");
+    a.ldr = ldr;
+    hipError_t e = adop::tonemap_forward(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "tone mapper forward");
+    return ADOP_OK;
+}
+
+adop_status adop_tonemap_backward(adop_context* ctx, const float* hdr, int32_t V, int32_t width, int32_t height,
+                                  const adop_tonemap* tm, const float* grad_ldr, float* grad_hdr, double* d_ev,
+                                  double* d_white, double* d_vignette, double* d_crf, void* workspace,
+                                  size_t workspace_bytes_, void* stream) {
+    adop::TonemapArgs a;
+    adop_status s = check_tonemap(ctx, hdr, V, width, height, tm, &a);
+    if (s) return s;
+    if (!grad_ldr || !grad_hdr || !d_ev || !d_white || !d_vignette || !d_crf)
+        return fail(ctx, ADOP_E_INVALID, "NULL gradient buffer");
+    if (!workspace) return fail(ctx, ADOP_E_WORKSPACE, "workspace is NULL");
+    if (workspace_bytes_ < adop_tonemap_workspace_bytes(V))
+        return fail(ctx, ADOP_E_WORKSPACE, "workspace %zu bytes < %zu", workspace_bytes_,
+                    adop_tonemap_workspace_bytes(V));
+    if (((uintptr_t)workspace & 15) != 0) return fail(ctx, ADOP_E_INVALID, "workspace must be 16-byte aligned");
+    a.grad = grad_ldr; a.d_hdr = grad_hdr; a.d_ev = d_ev; a.d_white = d_white; a.d_vig = d_vignette; a.d_crf = d_crf;
+    a.partials = static_cast<double*>(workspace);
+    hipError_t e = adop::tonemap_backward(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "tone mapper backward");
+    return ADOP_OK;
+}
+
 adop_status adop_scene_prepare(adop_context* ctx, const float* pos, const void* feat, int64_t n, int32_t channels,
                                adop_dtype dtype, int32_t block, uint64_t seed, float* x, float* y, float* z,
                                void* feat_out, int32_t* orig_index, void* stream) {

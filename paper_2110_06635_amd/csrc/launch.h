@@ -89,6 +89,26 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t st);
 hipError_t launch_backward(const BwdArgs& a, hipStream_t st);
 inline int pack_stride(int C) { return (C + 4 + 3) / 4 * 4; }
 
+// Photometric tone mapper (Sec. 3.3) of V 3-channel images [V][3][h][w].
+struct TonemapArgs {
+    int V, w, h, K;
+    float leak;                 // >= 0 leaky response, < 0 clamp
+    const float* hdr;
+    const float* ev;            // [V]
+    const float* white;         // [V][3]
+    const float* vig;           // [5] a2, a4, a6, cx, cy
+    const float* crf;           // [3][K]
+    float* ldr;                 // forward output
+    const float* grad;          // backward: dL/dldr
+    float* d_hdr;
+    double *d_ev, *d_white, *d_vig, *d_crf;
+    double* partials;           // workspace [V][kTonemapBlocks][16]
+};
+constexpr int kTonemapBlocks = 128;     // blocks per view (grid-stride over its pixels)
+constexpr int kTonemapMaxTable = 1024;  // largest response table (LDS gradient table of 3 K doubles)
+hipError_t tonemap_forward(const TonemapArgs& a, hipStream_t st);
+hipError_t tonemap_backward(const TonemapArgs& a, hipStream_t st);
+
 struct PrepArgs {
     int64_t n;
     int C, dtype, block;
