@@ -65,7 +65,7 @@ int oracle_project(const oracle_camera* cam, float x, float y, float z,
     return project_full(cam, x, y, z, &X, &Y, Zo, u0o, v0o);
 }
 
-static const oracle_options no_options = { 0u, NULL, NULL, NULL, 0.0f };
+static const oracle_options no_options = { 0u, NULL, NULL, NULL, 0.0f, NULL };
 
 /* Eq. normalculling for point i in a view (see ORACLE_CULL_*). */
 static int kept_by_normal(const oracle_camera* cam, const oracle_options* opt, int64_t i,
@@ -236,11 +236,13 @@ static int64_t img_index(const raster_state* st, const oracle_camera* cam, int v
 }
 
 /* Eq. blend: the mean of the features over Lambda, or the background where
- * Lambda is empty (a constant background stands in for the environment map). */
-static double blended(const raster_state* st, int64_t idx, int c, int ch, const float* background)
+ * Lambda is empty: the environment map's value at this pixel (bg_image, at
+ * image index o) or a constant background standing in for it. */
+static double blended(const raster_state* st, int64_t idx, int c, int ch, const float* background,
+                      const double* bg_image, int64_t o)
 {
     int32_t k = st->counts[idx];
-    if (k == 0) return (double)background[ch];
+    if (k == 0) return bg_image ? bg_image[o] : (double)background[ch];
     return st->sums[idx * c + ch] / (double)k;
 }
 
@@ -278,8 +280,8 @@ int oracle_forward_ex(int64_t n, int32_t c, const float* pos, const float* feat,
                 for (int32_t px = 0; px < wl; ++px) {
                     int64_t idx = st.vbase[v] + layer_offset(cam, l) + (int64_t)py * wl + px;
                     for (int ch = 0; ch < c; ++ch) {
-                        double m = blended(&st, idx, c, ch, background);
                         int64_t o = img_index(&st, cam, v, l, c, ch, px, py);
+                        double m = blended(&st, idx, c, ch, background, opt->bg_image, o);
                         images[o] = (float)m;
                         if (images64) images64[o] = m;
                     }
@@ -302,7 +304,7 @@ int oracle_forward_ex(int64_t n, int32_t c, const float* pos, const float* feat,
  * writes a magnitude bound of that dot product into *mag. */
 static double induced(const raster_state* st, const oracle_camera* cam, int v, int l, int c,
                       int32_t qx, int32_t qy, float Z, float fa, const double* tau,
-                      const float* background, const float* grad, double* mag)
+                      const float* background, const double* bg_image, const float* grad, double* mag)
 {
     int32_t wl = cam->width >> l, hl = cam->height >> l;
     *mag = 0.0;
@@ -313,10 +315,12 @@ static double induced(const raster_state* st, const oracle_camera* cam, int v, i
     if (nq == 0) {
         /* case 1: background is replaced by the point's texture */
         for (int ch = 0; ch < c; ++ch) {
-            double g = (double)grad[img_index(st, cam, v, l, c, ch, qx, qy)];
-            double dI = tau[ch] - (double)background[ch];
+            int64_t o = img_index(st, cam, v, l, c, ch, qx, qy);
+            double g = (double)grad[o];
+            double b = bg_image ? bg_image[o] : (double)background[ch];
+            double dI = tau[ch] - b;
             dot += g * dI;
-            m += fabs(g) * (fabs(tau[ch]) + fabs((double)background[ch]));
+            m += fabs(g) * (fabs(tau[ch]) + fabs(b));
         }
         *mag = m;
         return dot;
@@ -327,8 +331,9 @@ static double induced(const raster_state* st, const oracle_camera* cam, int v, i
     if (Z > behind) return 0.0;                      /* case 2: hidden behind q */
     if (front < minz) {                              /* case 3: replaces q's colour */
         for (int ch = 0; ch < c; ++ch) {
-            double g = (double)grad[img_index(st, cam, v, l, c, ch, qx, qy)];
-            double I = blended(st, q, c, ch, background);
+            int64_t o = img_index(st, cam, v, l, c, ch, qx, qy);
+            double g = (double)grad[o];
+            double I = blended(st, q, c, ch, background, bg_image, o);
             dot += g * (tau[ch] - I);
             m += fabs(g) * (fabs(tau[ch]) + fabs(I));
         }
@@ -337,8 +342,9 @@ static double induced(const raster_state* st, const oracle_camera* cam, int v, i
     }
     /* case 4: joins q's blend set; new mean minus old mean */
     for (int ch = 0; ch < c; ++ch) {
-        double g = (double)grad[img_index(st, cam, v, l, c, ch, qx, qy)];
-        double I = blended(st, q, c, ch, background);
+        int64_t o = img_index(st, cam, v, l, c, ch, qx, qy);
+        double g = (double)grad[o];
+        double I = blended(st, q, c, ch, background, bg_image, o);
         double Inew = ((double)nq * I + tau[ch]) / (double)(nq + 1);
         dot += g * (Inew - I);
         m += fabs(g) * (fabs(tau[ch]) + fabs(I)) / (double)(nq + 1);
@@ -422,10 +428,10 @@ int oracle_backward_ex(int64_t n, int32_t c, const float* pos, const float* feat
                 /* Eq. gradp: average of the induced changes of a shift by +1 and
                  * by -1 pixel; the -1 shift divides by Delta u = -1. */
                 double mr, ml, md, mu;
-                double right = induced(&st, cam, v, l, c, px + 1, py, Z, fa, tau, background, grad, &mr);
-                double left = induced(&st, cam, v, l, c, px - 1, py, Z, fa, tau, background, grad, &ml);
-                double down = induced(&st, cam, v, l, c, px, py + 1, Z, fa, tau, background, grad, &md);
-                double up = induced(&st, cam, v, l, c, px, py - 1, Z, fa, tau, background, grad, &mu);
+                double right = induced(&st, cam, v, l, c, px + 1, py, Z, fa, tau, background, opt->bg_image, grad, &mr);
+                double left = induced(&st, cam, v, l, c, px - 1, py, Z, fa, tau, background, opt->bg_image, grad, &ml);
+                double down = induced(&st, cam, v, l, c, px, py + 1, Z, fa, tau, background, opt->bg_image, grad, &md);
+                double up = induced(&st, cam, v, l, c, px, py - 1, Z, fa, tau, background, opt->bg_image, grad, &mu);
                 double du = 0.5 * (right - left);
                 double dv = 0.5 * (down - up);
                 /* u_l = 2^-l u0: chain to layer-0 pixel coordinates */

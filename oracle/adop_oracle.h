@@ -61,13 +61,18 @@ typedef struct oracle_camera {
 #define ORACLE_DISCARD 16u
 
 /* Options of the extended passes.  normals [n][3] (culling), radius [n] and
- * beta [n] (discarding) may be NULL when the matching flag is off. */
+ * beta [n] (discarding) may be NULL when the matching flag is off.
+ * bg_image (optional, float64 in the image layout [C * pixels]): the value
+ * of every pixel where Lambda is empty -- the environment map sampled
+ * through the inverse camera, E(R^T C^-1(u, v)) of Eq. blend -- used by the
+ * blend and by case 1 of Eq. spatialderiv; NULL: the constant background. */
 typedef struct oracle_options {
     uint32_t flags;
     const float* normals;
     const float* radius;
     const float* beta;
     float gamma;
+    const double* bg_image;
 } oracle_options;
 
 /* Projection of one point (FP32 arithmetic, stated formula).  Returns 1 and

@@ -25,7 +25,7 @@ DISCARD = 16
 
 class OracleOptions(ct.Structure):
     _fields_ = [("flags", ct.c_uint32), ("normals", ct.c_void_p), ("radius", ct.c_void_p),
-                ("beta", ct.c_void_p), ("gamma", ct.c_float)]
+                ("beta", ct.c_void_p), ("gamma", ct.c_float), ("bg_image", ct.c_void_p)]
 
 
 class OracleCamera(ct.Structure):
@@ -125,7 +125,7 @@ def total_pixels(cams, layers: int) -> int:
     return int(lib().oracle_total_pixels(cc, len(cams), layers))
 
 
-def _options(flags, normals, radius, beta, gamma):
+def _options(flags, normals, radius, beta, gamma, bg_image=None):
     """Options record plus the arrays it points to (kept alive by the caller)."""
     keep = []
     o = OracleOptions()
@@ -136,6 +136,10 @@ def _options(flags, normals, radius, beta, gamma):
             keep.append(a)
             setattr(o, name, a.ctypes.data)
     o.gamma = float(gamma)
+    if bg_image is not None:
+        b = np.ascontiguousarray(bg_image, dtype=np.float64)
+        keep.append(b)
+        o.bg_image = b.ctypes.data
     return o, keep
 
 
@@ -150,10 +154,12 @@ def knn_radius(pos):
 
 def forward(pos, feat, cams, layers: int, alpha: float = 0.01, background=None,
             want64: bool = False, flags: int = 0, normals=None, radius=None, beta=None,
-            gamma: float = 0.0):
+            gamma: float = 0.0, bg_image=None):
     """Returns dict(keys uint64, counts int32, images float32[, images64]).
     flags: CULL_BACKFACE / CULL_PRINTED (normals [n,3]), LOG_FEATURES,
-    DISCARD (radius [n], beta [n], gamma)."""
+    DISCARD (radius [n], beta [n], gamma).  bg_image: float64 values of
+    empty pixels in the image layout (the environment map's samples,
+    oracle.envmap.background_image); None: the constant background."""
     pos = np.ascontiguousarray(pos, dtype=np.float32)
     feat = np.ascontiguousarray(feat, dtype=np.float32)
     n, c = feat.shape
@@ -165,7 +171,9 @@ def forward(pos, feat, cams, layers: int, alpha: float = 0.01, background=None,
     counts = np.empty(total, np.int32)
     images = np.empty(total * c, np.float32)
     images64 = np.empty(total * c, np.float64) if want64 else None
-    opt, keep = _options(flags, normals, radius, beta, gamma)
+    if bg_image is not None:
+        assert np.asarray(bg_image).size == total * c
+    opt, keep = _options(flags, normals, radius, beta, gamma, bg_image)
     rc = lib().oracle_forward_ex(n, c, _p(pos), _p(feat), len(cams), cc, layers,
                                  ct.c_float(alpha), ct.byref(opt), _p(bg), _p(keys), _p(counts),
                                  _p(images), _p(images64))
@@ -179,7 +187,7 @@ def forward(pos, feat, cams, layers: int, alpha: float = 0.01, background=None,
 
 def backward(pos, feat, cams, layers: int, grad, alpha: float = 0.01, background=None,
              flags: int = 0, want_abs: bool = True, want_g: bool = False, normals=None,
-             radius=None, beta=None, gamma: float = 0.0):
+             radius=None, beta=None, gamma: float = 0.0, bg_image=None):
     """Returns dict(dfeat [n,c], dpos [3,n], dpose [V,6], dintr [V,9]) in float64,
     plus *_abs magnitude bounds and per-point gu/gv [V,n] on request."""
     pos = np.ascontiguousarray(pos, dtype=np.float32)
@@ -199,7 +207,9 @@ def backward(pos, feat, cams, layers: int, grad, alpha: float = 0.01, background
     if want_g:
         out.update(gu=np.empty((V, n)), gv=np.empty((V, n)))
     g = out.get
-    opt, keep = _options(flags, normals, radius, beta, gamma)
+    if bg_image is not None:
+        assert np.asarray(bg_image).size == total * c
+    opt, keep = _options(flags, normals, radius, beta, gamma, bg_image)
     rc = lib().oracle_backward_ex(n, c, _p(pos), _p(feat), V, cc, layers, ct.c_float(alpha),
                                ct.byref(opt), _p(bg), _p(grad), _p(out["dfeat"]), _p(out["dpos"]),
                                _p(out["dpose"]), _p(out["dintr"]), _p(g("dfeat_abs")),

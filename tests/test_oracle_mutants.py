@@ -7,6 +7,7 @@ import subprocess
 
 import pytest
 
+import tests.test_oracle_envmap as envpins
 import tests.test_oracle_next as nxt
 import tests.test_oracle_pins as pins
 
@@ -27,9 +28,15 @@ MUTANTS = [
     ("case4_mean", "double Inew = ((double)nq * I + tau[ch]) / (double)(nq + 1);",
      "double Inew = ((double)nq * I + tau[ch]) / (double)(nq);",
      lambda O: pins.test_microscenes(O, MICRO["S4b_equal_depth_n3"])),
-    ("case1_background", "double dI = tau[ch] - (double)background[ch];",
+    ("case1_background", "double dI = tau[ch] - b;",
      "double dI = tau[ch];",
      lambda O: pins.test_microscenes(O, MICRO["S8_background"])),
+    ("bg_image_ignored", "if (k == 0) return bg_image ? bg_image[o] : (double)background[ch];",
+     "if (k == 0) return (double)background[ch];",
+     lambda O: envpins.test_empty_pixels_take_the_per_pixel_background(O)),
+    ("bg_image_case1_ignored", "double b = bg_image ? bg_image[o] : (double)background[ch];",
+     "double b = (double)background[ch];",
+     lambda O: envpins.test_empty_neighbour_uses_the_map_value(O)),
     ("dfeat_count", "dfeat[i * c + ch] += g / k * chain;", "dfeat[i * c + ch] += g * chain;",
      lambda O: pins.test_feature_gradient_finite_difference(O)),
     ("visible_gate", "if (!visible && !(flags & ORACLE_SPATIAL_ALL)) continue;",
