@@ -119,6 +119,26 @@ typedef struct adop_render_params {
      * then only supplies the image sizes (which must match the table's) and
      * its other fields are validated but not used.  NULL: the host cameras. */
     const struct adop_camera* cameras_device;
+    /* Optional environment map (Eq. blend: a pixel no point hits takes
+     * E(R^T C^-1(u, v))): device [C][S][S] FP32 of S x S texels, S >= 2.
+     * Pixel (x, y) of layer l is unprojected at layer-0 coordinates
+     * (x 2^l, y 2^l) through the pinhole and the distortion of the camera
+     * (the Brown-Conrady map inverted by 20 fixed-point steps from the
+     * distorted coordinates); the world ray d = R^T (a, b, 1) / |.| is looked
+     * up at longitude atan2(d_x, d_z) and colatitude arccos(d_y), i.e. texel
+     * coordinates s = (atan2(d_x, d_z) / 2pi + 1/2) S, t = arccos(d_y) / pi S
+     * with texel (i, j) centred at (i + 1/2, j + 1/2), bilinearly, wrapping
+     * in longitude and clamping in colatitude.  The same map must be given
+     * to the backward of the frame (empty neighbours of Eq. spatialderiv's
+     * case 1 then take its values).  NULL: the constant background. */
+    const float* env_map;
+    int32_t env_size;          /* S */
+    /* backward, with env_map: device [C][S][S] FP32 output, overwritten
+     * with dL/dE (the derivative of Eq. blend at the empty pixels, summed
+     * with FP32 atomics in an order that varies between runs); NULL: not
+     * computed.  No gradient reaches the pose or intrinsics through the
+     * lookup. */
+    float* env_grad;
 } adop_render_params;
 
 /* A prepared scene (see adop_scene_prepare).  The SoA position planes and the

@@ -46,7 +46,8 @@ class Camera(ct.Structure):
 
 class RenderParams(ct.Structure):
     _fields_ = [("layers", ct.c_int32), ("alpha", ct.c_float), ("flags", ct.c_uint32),
-                ("background", ct.c_void_p), ("gamma", ct.c_float), ("cameras_device", ct.c_void_p)]
+                ("background", ct.c_void_p), ("gamma", ct.c_float), ("cameras_device", ct.c_void_p),
+                ("env_map", ct.c_void_p), ("env_size", ct.c_int32), ("env_grad", ct.c_void_p)]
 
 
 MAX_LAYERS_ = 8
@@ -365,15 +366,23 @@ GAMMA = 1.5   # the paper's discarding parameter
 
 
 def _params(layers: int, alpha: float, flags: int, background, C: int, gamma: float = GAMMA,
-            cams_device: Optional[torch.Tensor] = None, V: int = 0):
+            cams_device: Optional[torch.Tensor] = None, V: int = 0, env_map: Optional[torch.Tensor] = None,
+            env_grad: Optional[torch.Tensor] = None):
     bg = None
     if background is not None:
         bg = (ct.c_float * C)(*[float(b) for b in np.asarray(background, np.float32).reshape(C)])
     if cams_device is not None:
         assert cams_device.is_cuda and cams_device.is_contiguous() and cams_device.dtype == torch.float32
         assert cams_device.numel() == V * CAMERA_FLOATS, "camera table must hold the views' cameras"
+    S = 0
+    if env_map is not None:
+        assert env_map.is_cuda and env_map.dtype == torch.float32 and env_map.is_contiguous()
+        assert env_map.dim() == 3 and env_map.shape[0] == C and env_map.shape[1] == env_map.shape[2]
+        S = int(env_map.shape[1])
+        if env_grad is not None:
+            assert env_grad.shape == env_map.shape and env_grad.dtype == torch.float32 and env_grad.is_contiguous()
     p = RenderParams(layers, float(np.float32(alpha)), flags, ct.cast(bg, ct.c_void_p) if bg is not None else None,
-                     float(np.float32(gamma)), _ptr(cams_device))
+                     float(np.float32(gamma)), _ptr(cams_device), _ptr(env_map), S, _ptr(env_grad))
     return p, bg
 
 
@@ -416,12 +425,14 @@ class Frame:
 def render_forward(ctx: Context, scene: Scene, cams, layers: int, alpha: float = 0.01, flags: int = 0,
                    background=None, frame: Optional[Frame] = None, stream=None,
                    workspace: Optional[torch.Tensor] = None, gamma: float = GAMMA,
-                   record_visibility: bool = True, cams_device: Optional[torch.Tensor] = None) -> Frame:
+                   record_visibility: bool = True, cams_device: Optional[torch.Tensor] = None,
+                   env_map: Optional[torch.Tensor] = None) -> Frame:
     """record_visibility: also write frame.visible ([V, n] uint8, bit l =
     the point is in layer l's blend set), which lets render_backward skip
     the points that blend nowhere; False leaves frame.visible unset.
     cams_device: a device camera table ([V, 25], cameras_upload) whose
-    intrinsics and poses replace those of `cams` (which give the sizes)."""
+    intrinsics and poses replace those of `cams` (which give the sizes).
+    env_map: [C, S, S] FP32 environment map sampled by the empty pixels."""
     C = scene.channels
     if frame is None:
         frame = Frame(cams, layers, C, scene.x.device)
@@ -439,7 +450,7 @@ def render_forward(ctx: Context, scene: Scene, cams, layers: int, alpha: float =
             frame.visible = torch.empty(shape, dtype=torch.uint8, device=scene.x.device)
     else:
         frame.visible = None
-    p, keep = _params(layers, alpha, flags, background, C, gamma, cams_device, len(frame.cams))
+    p, keep = _params(layers, alpha, flags, background, C, gamma, cams_device, len(frame.cams), env_map)
     sd = scene.desc()
     fd = frame.desc()
     st = lib().adop_render_forward(ctx.handle, ct.byref(sd), frame.cams, len(frame.cams), ct.byref(p),
@@ -473,9 +484,12 @@ def render_forward_noalloc(ctx: Context, scene: Scene, frame: Frame, alpha: floa
 def render_backward(ctx: Context, scene: Scene, frame: Frame, grad: torch.Tensor, alpha: float = 0.01,
                     flags: int = 0, background=None, stream=None, out=None,
                     workspace: Optional[torch.Tensor] = None, gamma: float = GAMMA,
-                    cams_device: Optional[torch.Tensor] = None):
+                    cams_device: Optional[torch.Tensor] = None, env_map: Optional[torch.Tensor] = None,
+                    env_grad: Optional[torch.Tensor] = None):
     """Returns (dfeat [n,C] f32, dpos [3,n] f32, dpose [V,6] f64, dintr [V,9] f64).
-    cams_device: the camera table the forward of this frame used, if any."""
+    cams_device: the camera table the forward of this frame used, if any.
+    env_map: the forward's environment map; env_grad: [C, S, S] FP32 output
+    for its gradient (or None)."""
     C = scene.channels
     V = len(frame.cams)
     dev = scene.x.device
@@ -490,7 +504,7 @@ def render_backward(ctx: Context, scene: Scene, frame: Frame, grad: torch.Tensor
     if frame.visible is not None and tuple(frame.visible.shape) != (V, scene.n):
         raise ValueError("frame.visible was recorded for another scene")
     ws = workspace if workspace is not None else ctx.workspace(C, V, frame.pixels)
-    p, keep = _params(frame.layers, alpha, flags, background, C, gamma, cams_device, V)
+    p, keep = _params(frame.layers, alpha, flags, background, C, gamma, cams_device, V, env_map, env_grad)
     sd = scene.desc()
     fd = frame.desc()
     st = lib().adop_render_backward(ctx.handle, ct.byref(sd), frame.cams, V, ct.byref(p), ct.byref(fd),

@@ -227,6 +227,10 @@ adop_status check_common(adop_context* ctx, const adop_scene* scene, const adop_
         if (!(params->gamma > 0.0f) || !std::isfinite(params->gamma))
             return fail(ctx, ADOP_E_INVALID, "stochastic discarding needs a finite gamma > 0");
     }
+    if (params->env_map && params->env_size < 2)
+        return fail(ctx, ADOP_E_INVALID, "env_size=%d must be >= 2 with an environment map", params->env_size);
+    if (params->env_map && (int64_t)params->env_size * params->env_size >= ((int64_t)1 << 31))
+        return fail(ctx, ADOP_E_UNSUPPORTED, "env_size=%d too large", params->env_size);
     if (!frame || !frame->images || !frame->keys || !frame->counts) return fail(ctx, ADOP_E_INVALID, "frame has a NULL buffer");
     layout(cams, V, params->layers, total, nullptr);
     if (frame->pixels != *total)
@@ -360,6 +364,8 @@ adop::FwdArgs fwd_args(adop_context* ctx, const adop_scene* scene, const adop_ca
     a.sums = reinterpret_cast<float*>(static_cast<unsigned char*>(ws) + views_region(V));
     a.images = frame->images;
     a.background = params->background;
+    a.env = params->env_map;
+    a.env_size = params->env_map ? params->env_size : 0;
     a.opts = point_opts(scene, params);
     a.timer = timer_of(ctx);
     a.vis = frame->visible;
@@ -752,6 +758,9 @@ adop_status adop_render_backward(adop_context* ctx, const adop_scene* scene, con
     a.dpose = dpose;
     a.dintr = dintr;
     a.background = params->background;
+    a.env = params->env_map;
+    a.env_size = params->env_map ? params->env_size : 0;
+    a.env_grad = params->env_map ? params->env_grad : nullptr;
     a.opts = point_opts(scene, params);
     a.timer = timer_of(ctx);
     a.vis = frame->visible;

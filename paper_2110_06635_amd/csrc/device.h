@@ -211,6 +211,61 @@ __device__ __forceinline__ uint32_t discard_mask(const PointOpts& o, const CamT&
 }
 
 // ----------------------------------------------------------------------------
+// environment map (Eq. blend: an empty pixel takes E(R^T C^-1(u, v)))
+// ----------------------------------------------------------------------------
+// Pixel (x, y) of layer l sits at layer-0 coordinates (x 2^l, y 2^l); C^-1
+// inverts the pinhole and, with kUndistortIters fixed-point steps from the
+// distorted coordinates, the Brown-Conrady map of project(); the world ray
+// R^T (a, b, 1) is looked up in an equirectangular map of S x S texels
+// (longitude atan2(d_x, d_z), colatitude arccos(d_y)), bilinearly between
+// texel centres, wrapping in longitude and clamping in colatitude.
+constexpr int kUndistortIters = 20;
+
+struct EnvTaps {
+    uint32_t idx[4];   // texel index r * S + c of the four taps
+    float w[4];
+};
+
+template <typename CamT>
+__device__ __forceinline__ EnvTaps env_taps(const CamT& c, int l, int x, int y, int S) {
+    const float s2 = (float)(1 << l);
+    const float xd = ((float)x * s2 - c.cx) / c.fx;
+    const float yd = ((float)y * s2 - c.cy) / c.fy;
+    float a = xd, b = yd;
+    for (int it = 0; it < kUndistortIters; ++it) {
+        const float r2 = a * a + b * b;
+        const float D = 1.0f + r2 * (c.k1 + r2 * (c.k2 + r2 * c.k3));
+        const float dx = 2.0f * c.p1 * a * b + c.p2 * (r2 + 2.0f * a * a);
+        const float dy = 2.0f * c.p2 * a * b + c.p1 * (r2 + 2.0f * b * b);
+        a = (xd - dx) / D;
+        b = (yd - dy) / D;
+    }
+    float wx = c.R[0] * a + c.R[3] * b + c.R[6];
+    float wy = c.R[1] * a + c.R[4] * b + c.R[7];
+    float wz = c.R[2] * a + c.R[5] * b + c.R[8];
+    const float inv = 1.0f / sqrtf(wx * wx + wy * wy + wz * wz);
+    wx *= inv;
+    wy *= inv;
+    wz *= inv;
+    const float kInv2Pi = 0.159154943091895336f, kInvPi = 0.318309886183790672f;
+    const float sc = (atan2f(wx, wz) * kInv2Pi + 0.5f) * (float)S - 0.5f;
+    const float tc = acosf(fminf(fmaxf(wy, -1.0f), 1.0f)) * kInvPi * (float)S - 0.5f;
+    const float i0f = floorf(sc), j0f = floorf(tc);
+    const float fx = sc - i0f, fy = tc - j0f;
+    int i0 = (int)i0f % S;
+    if (i0 < 0) i0 += S;
+    const int i1 = i0 + 1 == S ? 0 : i0 + 1;
+    const int j0 = (int)j0f;
+    const int r0 = min(max(j0, 0), S - 1), r1 = min(max(j0 + 1, 0), S - 1);
+    EnvTaps t;
+    t.idx[0] = (uint32_t)(r0 * S + i0); t.w[0] = (1.0f - fx) * (1.0f - fy);
+    t.idx[1] = (uint32_t)(r0 * S + i1); t.w[1] = fx * (1.0f - fy);
+    t.idx[2] = (uint32_t)(r1 * S + i0); t.w[2] = (1.0f - fx) * fy;
+    t.idx[3] = (uint32_t)(r1 * S + i1); t.w[3] = fx * fy;
+    return t;
+}
+
+// ----------------------------------------------------------------------------
 // wave64 helpers
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return __lane_id(); }

@@ -48,6 +48,8 @@ struct FwdArgs {
     float* sums;       // workspace [pixels][C]
     float* images;
     const float* background;   // host [C] or null
+    const float* env = nullptr;   // optional environment map [C][S][S] (empty pixels sample it)
+    int env_size = 0;
     PointOpts opts;
     uint8_t* vis = nullptr;   // optional [V][n] blend-set bits per point and view
     Timer timer;
@@ -81,6 +83,9 @@ struct BwdArgs {
     double* dpose;
     double* dintr;
     const float* background;
+    const float* env = nullptr;     // environment map of the forward, if any
+    int env_size = 0;
+    float* env_grad = nullptr;      // optional [C][S][S] output: the map's gradient
     const uint8_t* vis = nullptr;   // optional [V][n], written by the forward
     Timer timer;
 };

@@ -39,6 +39,10 @@ void launch_depth(const FwdArgs& a, hipStream_t st) {
     a.timer.mark(kKDepth, 1, st);
 }
 
+void launch_fill_zero(float* p, int64_t n, hipStream_t st) {
+    k_fill_zero<<<(unsigned)std::min<int64_t>((n + 255) / 256, 4096), 256, 0, st>>>(p, n);
+}
+
 void launch_reduce(const BwdArgs& a, unsigned groups, hipStream_t st) {
     a.timer.mark(kKReduce, 0, st);
     k_reduce_slices<<<dim3(kReduceSlices, (unsigned)a.V), 256, 0, st>>>(a.partials, (int)groups, a.V, a.slices);

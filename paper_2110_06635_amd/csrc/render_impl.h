@@ -474,7 +474,8 @@ template <int C>
 __global__ void __launch_bounds__(256) k_normalize(const ViewRec* __restrict__ views, int L,
                                                    const float* __restrict__ sums, int64_t P,
                                                    const int32_t* __restrict__ counts,
-                                                   float* __restrict__ images, Background bg) {
+                                                   float* __restrict__ images, Background bg,
+                                                   const float* __restrict__ env, int S) {
     int vl = blockIdx.y;
     int v = vl / L, l = vl - (vl / L) * L;
     const ViewRec& c = views[v];
@@ -486,6 +487,21 @@ __global__ void __launch_bounds__(256) k_normalize(const ViewRec* __restrict__ v
         const float* s = sums + p;          // planar [C][pixels]
         const uint64_t cs = (uint64_t)P;   // channel stride
         float* out = images + (uint64_t)C * base + (uint64_t)j;
+        if (k == 0 && env != nullptr) {
+            const int lw = c.lw[l];
+            const EnvTaps t = env_taps(c, l, (int)(j % lw), (int)(j / lw), S);
+            const uint64_t plane = (uint64_t)S * (uint64_t)S;
+#pragma unroll
+            for (int ch = 0; ch < C; ++ch) {
+                const float* e = env + (uint64_t)ch * plane;
+                float val = t.w[0] * e[t.idx[0]];
+                val = __fmaf_rn(t.w[1], e[t.idx[1]], val);
+                val = __fmaf_rn(t.w[2], e[t.idx[2]], val);
+                val = __fmaf_rn(t.w[3], e[t.idx[3]], val);
+                out[(uint64_t)ch * (uint64_t)npx] = val;
+            }
+            continue;
+        }
 #pragma unroll
         for (int ch = 0; ch < C; ++ch) {
             float val = k > 0 ? __fdiv_rn(s[(uint64_t)ch * cs], (float)k) : bg.v[ch];
@@ -493,6 +509,43 @@ __global__ void __launch_bounds__(256) k_normalize(const ViewRec* __restrict__ v
         }
     }
 }
+
+// Gradient of the environment map (derivative of Eq. blend at the empty
+// pixels): every empty pixel adds G(p) times its four bilinear weights to
+// the texels it sampled (FP32 atomics; the order varies between runs).
+template <int C>
+__global__ void __launch_bounds__(256) k_env_grad(const ViewRec* __restrict__ views, int L,
+                                                  const int32_t* __restrict__ counts,
+                                                  const float* __restrict__ grad, float* __restrict__ env_grad,
+                                                  int S) {
+    int vl = blockIdx.y;
+    int v = vl / L, l = vl - (vl / L) * L;
+    const ViewRec& c = views[v];
+    int64_t npx = (int64_t)c.lw[l] * c.lh[l];
+    uint64_t base = c.base[l];
+    const uint64_t plane = (uint64_t)S * (uint64_t)S;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < npx; j += (int64_t)gridDim.x * blockDim.x) {
+        if (counts[base + (uint64_t)j] != 0) continue;
+        const int lw = c.lw[l];
+        const EnvTaps t = env_taps(c, l, (int)(j % lw), (int)(j / lw), S);
+        const float* g = grad + (uint64_t)C * base + (uint64_t)j;
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch) {
+            const float gc = g[(uint64_t)ch * (uint64_t)npx];
+            if (gc == 0.0f) continue;
+            float* e = env_grad + (uint64_t)ch * plane;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) atomic_add_f32(e + t.idx[q], gc * t.w[q]);
+        }
+    }
+}
+
+#ifdef ADOP_RENDER_BASE
+__global__ void __launch_bounds__(256) k_fill_zero(float* __restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+#endif  // ADOP_RENDER_BASE
 
 // ---------------------------------------------------------------------------
 // backward
@@ -504,7 +557,7 @@ __global__ void __launch_bounds__(256) k_pack(const ViewRec* __restrict__ views,
                                               const int32_t* __restrict__ counts,
                                               const float* __restrict__ images,
                                               const float* __restrict__ grad,
-                                              float* __restrict__ pack, float fa, Background bg) {
+                                              float* __restrict__ pack, float fa, Background bg, bool env) {
     using PL = PackLayout<C>;
     int vl = blockIdx.y;
     int v = vl / L, l = vl - (vl / L) * L;
@@ -522,7 +575,9 @@ __global__ void __launch_bounds__(256) k_pack(const ViewRec* __restrict__ views,
 #pragma unroll
         for (int ch = 0; ch < C; ++ch) {
             float g = gi[(uint64_t)ch * (uint64_t)npx];
-            float I = k > 0 ? ii[(uint64_t)ch * (uint64_t)npx] : bg.v[ch];
+            // an empty pixel's value: the environment map's sample (written
+            // by the forward into the image) or the constant background
+            float I = (k > 0 || env) ? ii[(uint64_t)ch * (uint64_t)npx] : bg.v[ch];
             rec[ch] = g;
             gdot = __fmaf_rn(g, I, gdot);
         }
@@ -1012,6 +1067,7 @@ static inline unsigned range_grid(int64_t n, int64_t range, unsigned at_least) {
 void launch_clear(const FwdArgs& a, int64_t nsums, hipStream_t st);
 void launch_depth(const FwdArgs& a, hipStream_t st);
 void launch_reduce(const BwdArgs& a, unsigned groups, hipStream_t st);
+void launch_fill_zero(float* p, int64_t n, hipStream_t st);
 
 template <int C, typename S, bool SINGLE, bool OPTS, int LN>
 static void accum_pass(const FwdArgs& a, hipStream_t st) {
@@ -1055,7 +1111,8 @@ static hipError_t forward_impl(const FwdArgs& a, hipStream_t st) {
     }
     dim3 gn((unsigned)std::min<int64_t>((a.max_layer_pixels + 255) / 256, 1024), (unsigned)(a.V * a.L));
     a.timer.mark(kKNormalize, 0, st);
-    k_normalize<C><<<gn, 256, 0, st>>>(a.views, a.L, a.sums, a.pixels, a.counts, a.images, make_bg(a.background, C));
+    k_normalize<C><<<gn, 256, 0, st>>>(a.views, a.L, a.sums, a.pixels, a.counts, a.images, make_bg(a.background, C),
+                                       a.env, a.env_size);
     a.timer.mark(kKNormalize, 1, st);
     return hipGetLastError();
 }
@@ -1088,7 +1145,11 @@ static hipError_t backward_impl(const BwdArgs& a, hipStream_t st) {
     dim3 gn((unsigned)std::min<int64_t>((a.max_layer_pixels + 255) / 256, 1024), (unsigned)(a.V * a.L));
     a.timer.mark(kKPack, 0, st);
     k_pack<C><<<gn, 256, 0, st>>>(a.views, a.L, a.keys, a.counts, a.images, a.grad, a.pack, a.fa,
-                                 make_bg(a.background, C));
+                                 make_bg(a.background, C), a.env != nullptr);
+    if (a.env != nullptr && a.env_grad != nullptr) {
+        launch_fill_zero(a.env_grad, (int64_t)C * a.env_size * a.env_size, st);
+        k_env_grad<C><<<gn, 256, 0, st>>>(a.views, a.L, a.counts, a.grad, a.env_grad, a.env_size);
+    }
     a.timer.mark(kKPack, 1, st);
     const bool opts = a.opts.flags != 0;
     unsigned g = a.V == 1 ? (opts ? backward_points<C, S, true, true>(a, st) : backward_points<C, S, true, false>(a, st))
