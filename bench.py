@@ -101,6 +101,30 @@ def l1_grad(frame, target):
     return G
 
 
+def atomic_ceiling(ctx):
+    """The device's atomic throughput for the two kinds the render passes use
+    (u64 minimum: depth pass, FP32 add: accumulation), 2^28 ops each:
+    scattered over a 1 GiB buffer one cache line per lane (what HBM-resident
+    pixel buffers see), over 2 MiB (L2-resident), and on 64 words (heavy
+    contention, as on the hot pixels of coarse layers).  Ops per second."""
+    import torch
+    from paper_2110_06635_amd import adop
+    buf = torch.zeros(1 << 30, dtype=torch.uint8, device="cuda:0")
+    ops = 1 << 28
+    out = {"ops_per_case": ops}
+    for kind, name, word in ((0, "u64_min", 8), (1, "f32_add", 4)):
+        stride = 128 // word
+        cases = {"scattered_hbm": ((1 << 30) // word, stride), "scattered_l2": ((2 << 20) // word, stride),
+                 "contended_64_words": (64, 1)}
+        for case, (fp, sd) in cases.items():
+            adop.atomic_probe(ctx, kind, ops >> 4, fp, sd, buf)          # warm-up
+            ms = adop.atomic_probe(ctx, kind, ops, fp, sd, buf)
+            out[f"{name}_{case}"] = round(ops / (ms * 1e-3), 1)
+    del buf
+    torch.cuda.empty_cache()
+    return out
+
+
 def host_cpu():
     """Host CPU model name and logical CPU count."""
     model = ""
@@ -419,6 +443,7 @@ def main():
         abv = algorithmic_bytes(n, C, rv["s"], rv["phi"], rv["pixels"])
         variants[vd] = {"value": n * V / (rv["ms"] * 1e-3), "ms_per_step": round(rv["ms"], 4),
                         "step_frac_of_hbm_roofline": round(sum(abv.values()) / (rv["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    atomics = atomic_ceiling(ctx) if (args.workload == "gmm100m" and not options) else None
     cpu = None
     if not args.no_cpu and V == 1 and not options:
         log(f"cpu baseline on {args.cpu_sample} points, then all cores")
@@ -460,6 +485,7 @@ def main():
         "preprocess": r["pre"],
         "precision_variants": variants,
         "serving": serving,
+        "atomic_ceiling": atomics,
     }
     print(json.dumps(line), flush=True)
 

@@ -384,6 +384,21 @@ adop_status adop_tonemap_backward(adop_context* ctx, const float* hdr, int32_t V
                                   float* grad_hdr, double* d_ev, double* d_white, double* d_vignette,
                                   double* d_crf, void* workspace, size_t workspace_bytes, void* stream);
 
+/* ------------------------------------------------ atomic throughput */
+/* Diagnostic (Sec. 3.1 "Implementation Details": the depth pass and the
+ * accumulation pass are built on atomics): times `ops` device atomics of one
+ * kind on the caller's device buffer -- kind 0: 64-bit unsigned minimum (the
+ * depth pass's key update), kind 1: FP32 add (the accumulation's sums).  Op i
+ * targets word (i * stride) mod footprint (8-byte words for kind 0, 4-byte
+ * for kind 1; consecutive lanes take consecutive ops), so stride 32 with a
+ * large footprint scatters every lane to its own cache line, a small
+ * footprint stays in the caches and footprint 1 contends on one word.  The
+ * buffer's contents are overwritten.  Enqueues the kernel between two events
+ * on `stream`, waits for them and writes the kernel's duration in
+ * milliseconds to *ms. */
+adop_status adop_atomic_probe(adop_context* ctx, int32_t kind, int64_t ops, int64_t footprint, int64_t stride,
+                              void* buffer, size_t buffer_bytes, double* ms, void* stream);
+
 /* ------------------------------------------------ per-kernel timing */
 /* When enabled, every kernel a render call enqueues is bracketed by HIP
  * events recorded on the same stream.  adop_timing_read waits for the

@@ -108,6 +108,8 @@ def lib():
         L.adop_scene_bind.argtypes = [P, I64, I32, I32, P]
         L.adop_cameras_upload.restype = S
         L.adop_cameras_upload.argtypes = [P, P, I32, P, P]
+        L.adop_atomic_probe.restype = S
+        L.adop_atomic_probe.argtypes = [P, I32, I64, I64, I64, P, ct.c_size_t, P, P]
         L.adop_tonemap_forward.restype = S
         L.adop_tonemap_forward.argtypes = [P, P, I32, I32, I32, P, P, P]
         L.adop_tonemap_workspace_bytes.restype = ct.c_size_t
@@ -146,6 +148,7 @@ EXPORTS = ["adop_version", "adop_status_string", "adop_context_create", "adop_co
            "adop_last_error", "adop_views_layout", "adop_workspace_bytes", "adop_feature_bytes",
            "adop_pyramid_layout", "adop_scene_bytes", "adop_scene_bind", "adop_cameras_upload",
            "adop_tonemap_forward", "adop_tonemap_workspace_bytes", "adop_tonemap_backward",
+           "adop_atomic_probe",
            "adop_scene_prepare", "adop_scene_gather", "adop_knn_radius",
            "adop_render_forward", "adop_render_forward_noalloc", "adop_render_backward",
            "adop_forward_graph_create", "adop_forward_graph_launch", "adop_graph_destroy",
@@ -616,3 +619,14 @@ def tonemap_backward(ctx: Context, hdr: torch.Tensor, tm: Tonemapper, grad: torc
                                      _stream(stream))
     ctx.check(st, "adop_tonemap_backward")
     return d_hdr, d_ev, d_white, d_vig, d_crf
+
+
+def atomic_probe(ctx: Context, kind: int, ops: int, footprint: int, stride: int, buffer: torch.Tensor,
+                 stream=None) -> float:
+    """Duration in ms of `ops` device atomics (kind 0: u64 minimum, 1: FP32
+    add) on words (i * stride) mod footprint of `buffer` (adop_atomic_probe)."""
+    ms = ct.c_double()
+    st = lib().adop_atomic_probe(ctx.handle, kind, ops, footprint, stride, _ptr(buffer),
+                                 buffer.numel() * buffer.element_size(), ct.byref(ms), _stream(stream))
+    ctx.check(st, "adop_atomic_probe")
+    return float(ms.value)

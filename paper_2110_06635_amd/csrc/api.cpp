@@ -565,6 +565,38 @@ adop_status adop_cameras_upload(adop_context* ctx, const adop_camera* host, int3
     return ADOP_OK;
 }
 
+adop_status adop_atomic_probe(adop_context* ctx, int32_t kind, int64_t ops, int64_t footprint, int64_t stride,
+                              void* buffer, size_t buffer_bytes, double* ms, void* stream) {
+    if (!ctx) return ADOP_E_INVALID;
+    ctx->err.clear();
+    if (kind != 0 && kind != 1) return fail(ctx, ADOP_E_INVALID, "kind %d is not 0 (u64 min) or 1 (f32 add)", kind);
+    if (ops < 1 || footprint < 1 || stride < 1 || !buffer || !ms)
+        return fail(ctx, ADOP_E_INVALID, "ops, footprint, stride must be >= 1 and pointers non-NULL");
+    const size_t word = kind == 0 ? 8 : 4;
+    if ((size_t)footprint > buffer_bytes / word)
+        return fail(ctx, ADOP_E_INVALID, "footprint %lld words exceeds the buffer", (long long)footprint);
+    if (((uintptr_t)buffer & (word - 1)) != 0) return fail(ctx, ADOP_E_INVALID, "buffer misaligned");
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e;
+    auto done = [&](adop_status s) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        return s;
+    };
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
+        return done(hip_fail(ctx, e, "hipEventCreate"));
+    if ((e = hipEventRecord(e0, st)) != hipSuccess) return done(hip_fail(ctx, e, "hipEventRecord"));
+    if ((e = adop::atomic_probe(kind, ops, footprint, stride, buffer, ctx->cus, st)) != hipSuccess)
+        return done(hip_fail(ctx, e, "atomic probe"));
+    if ((e = hipEventRecord(e1, st)) != hipSuccess) return done(hip_fail(ctx, e, "hipEventRecord"));
+    if ((e = hipEventSynchronize(e1)) != hipSuccess) return done(hip_fail(ctx, e, "hipEventSynchronize"));
+    float t = 0.f;
+    if ((e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) return done(hip_fail(ctx, e, "hipEventElapsedTime"));
+    *ms = t;
+    return done(ADOP_OK);
+}
+
 size_t adop_tonemap_workspace_bytes(int32_t V) {
     if (V < 1 || V > ADOP_MAX_VIEWS) return 0;
     return (size_t)V * adop::kTonemapBlocks * 16 * sizeof(double);

@@ -94,6 +94,11 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t st);
 hipError_t launch_backward(const BwdArgs& a, hipStream_t st);
 inline int pack_stride(int C) { return (C + 4 + 3) / 4 * 4; }
 
+// Atomic-throughput probe: `ops` atomics of one kind (0: u64 minimum, 1: FP32
+// add) on words (i * stride) mod footprint of `buf`.
+hipError_t atomic_probe(int kind, int64_t ops, int64_t footprint, int64_t stride, void* buf, int cus,
+                        hipStream_t st);
+
 // Photometric tone mapper (Sec. 3.3) of V 3-channel images [V][3][h][w].
 struct TonemapArgs {
     int V, w, h, K;

@@ -50,6 +50,27 @@ void launch_reduce(const BwdArgs& a, unsigned groups, hipStream_t st) {
     a.timer.mark(kKReduce, 1, st);
 }
 
+// Atomic-throughput probe (diagnostic): op i targets word (i * stride) mod
+// footprint; consecutive lanes take consecutive ops.
+__global__ void __launch_bounds__(256) k_atomic_probe(int kind, int64_t ops, int64_t footprint, int64_t stride,
+                                                      void* __restrict__ buf) {
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ops; i += step) {
+        const int64_t w = (i * stride) % footprint;
+        if (kind == 0)
+            atomic_min_u64(static_cast<uint64_t*>(buf) + w, (uint64_t)(ops - i));
+        else
+            atomic_add_f32(static_cast<float*>(buf) + w, 1.0f);
+    }
+}
+
+hipError_t atomic_probe(int kind, int64_t ops, int64_t footprint, int64_t stride, void* buf, int cus,
+                        hipStream_t st) {
+    const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((ops + 255) / 256, (int64_t)cus * 32));
+    k_atomic_probe<<<g, 256, 0, st>>>(kind, ops, footprint, stride, buf);
+    return hipGetLastError();
+}
+
 hipError_t launch_forward(const FwdArgs& a, hipStream_t st) {
     if (a.C < 1 || a.C > 16) return hipErrorInvalidValue;
     switch ((a.C - 1) / 4) {

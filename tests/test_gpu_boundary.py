@@ -158,3 +158,22 @@ def test_autograd_step_without_host_sync(env):
         np.testing.assert_allclose(tab[v, 22:25], np.asarray(c.t, np.float32).reshape(3), rtol=1e-6, atol=1e-6)
         np.testing.assert_array_equal(tab[v, 2:11], np.float32([getattr(c, k) for k in
                                                                  ("fx", "fy", "cx", "cy", "k1", "k2", "k3", "p1", "p2")]))
+
+
+def test_atomic_probe_results(env):
+    """The diagnostic atomics do what they time: each word holds the minimum
+    (kind 0) or the count (kind 1) of the ops that targeted it."""
+    torch, A, ctx = env
+    ops, fp = 1 << 20, 64
+    buf = torch.full((fp,), -1, dtype=torch.int64, device="cuda:0")     # all ones: u64 maximum
+    ms = A.atomic_probe(ctx, 0, ops, fp, 1, buf)
+    torch.cuda.synchronize()
+    got = buf.cpu().numpy().view(np.uint64)
+    want = np.array([ops - (ops - fp + w) for w in range(fp)], dtype=np.uint64)   # ops - largest i with i % fp == w
+    assert ms > 0 and np.array_equal(got, want)
+    fbuf = torch.zeros(fp, dtype=torch.float32, device="cuda:0")
+    A.atomic_probe(ctx, 1, ops, fp, 1, fbuf)
+    torch.cuda.synchronize()
+    assert bool((fbuf == ops // fp).all())
+    with pytest.raises(A.AdopError):
+        A.atomic_probe(ctx, 0, ops, 1 << 20, 1, buf)        # footprint beyond the buffer
