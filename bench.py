@@ -125,6 +125,30 @@ def atomic_ceiling(ctx):
     return out
 
 
+def atomic_sweep(ctx):
+    """Atomic throughput against the spacing of consecutive lanes' words
+    (1 GiB buffer, 2^28 ops per case): with a spacing below one 64-byte line
+    several lanes share one L2 request, so ops/s divided by the lanes per
+    request gives the L2's request rate for the kind."""
+    import torch
+    from paper_2110_06635_amd import adop
+    buf = torch.zeros(1 << 30, dtype=torch.uint8, device="cuda:0")
+    ops = 1 << 28
+    rows = []
+    for kind, name, word in ((1, "f32_add", 4), (0, "u64_min", 8)):
+        for stride in (1, 2, 4, 8, 16, 32):
+            fp = (1 << 30) // word
+            adop.atomic_probe(ctx, kind, ops >> 4, fp, stride, buf)      # warm-up
+            ms = adop.atomic_probe(ctx, kind, ops, fp, stride, buf)
+            per_req = max(1, 64 // (word * stride))
+            rows.append({"kind": name, "stride_words": stride, "lanes_per_64B": per_req,
+                         "ops_per_s": round(ops / (ms * 1e-3), 1),
+                         "requests_per_s": round(ops / per_req / (ms * 1e-3), 1), "ms": round(ms, 4)})
+    del buf
+    torch.cuda.empty_cache()
+    return rows
+
+
 def host_cpu():
     """Host CPU model name and logical CPU count."""
     model = ""
@@ -301,16 +325,25 @@ def main():
     ap.add_argument("--log-features", action="store_true", help="features are logarithmic descriptors")
     ap.add_argument("--no-visibility", action="store_true",
                     help="the forward records no blend-set bits; the backward re-tests every point")
+    ap.add_argument("--atomic-sweep", action="store_true",
+                    help="only measure atomic throughput against lane spacing, one JSON line per case")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+                                   "(multi-GPU sharding is not built)"}))
         sys.exit(2)
 
     if args.serve:
         serve_bench(args)
+        return
+    if args.atomic_sweep:
+        from paper_2110_06635_amd import adop
+        ctx = adop.Context(0)
+        for row in atomic_sweep(ctx):
+            print(json.dumps(row), flush=True)
+        print(json.dumps({"atomic_ceiling": atomic_ceiling(ctx)}), flush=True)
         return
 
     import numpy as np

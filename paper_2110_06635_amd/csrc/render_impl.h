@@ -682,18 +682,33 @@ __device__ __forceinline__ float induced_rec(const float (&rec)[PackLayout<C>::s
 // A layer where the point is in its pixel's blend set (or every in-bounds
 // point with SPATIAL_ALL): the own record and the four neighbour records are
 // loaded together, then dtau += G/n (if vis) and dL/du, dL/dv.
-template <int C>
+template <int C, bool UNI>
 __device__ __forceinline__ void layer_work(const float* __restrict__ pack, uint32_t pix, int qx, int qy, int lw,
                                            int lh, float Z, float fa, bool vis, const float (&tau)[C],
                                            float (&dt)[C], float& du, float& dv) {
     using PL = PackLayout<C>;
     float own[PL::stride], rr[PL::stride], rl[PL::stride], rd[PL::stride], ru[PL::stride];
+    const uint32_t p0 = __builtin_amdgcn_readfirstlane(pix);
+    if (UNI && ballot(pix != p0) == 0) {
+        // every working lane is on one pixel (a wave's points share a
+        // cluster): its five records are read once for the wave through
+        // scalar loads instead of once per lane.  One view only: with several
+        // views the branch costs the kernel a wave per SIMD.
+        const int sx = __builtin_amdgcn_readfirstlane(qx), sy = __builtin_amdgcn_readfirstlane(qy);
+        const uint64_t q = p0;
+        load_rec<C>(pack, q, own);
+        load_rec<C>(pack, sx + 1 < lw ? q + 1 : q, rr);
+        load_rec<C>(pack, sx > 0 ? q - 1 : q, rl);
+        load_rec<C>(pack, sy + 1 < lh ? q + (uint64_t)lw : q, rd);
+        load_rec<C>(pack, sy > 0 ? q - (uint64_t)lw : q, ru);
+    } else {
+        load_rec<C>(pack, pix, own);
+        load_rec<C>(pack, qx + 1 < lw ? (uint64_t)pix + 1 : (uint64_t)pix, rr);
+        load_rec<C>(pack, qx > 0 ? (uint64_t)pix - 1 : (uint64_t)pix, rl);
+        load_rec<C>(pack, qy + 1 < lh ? (uint64_t)pix + lw : (uint64_t)pix, rd);
+        load_rec<C>(pack, qy > 0 ? (uint64_t)pix - lw : (uint64_t)pix, ru);
+    }
     const bool hr = qx + 1 < lw, hl = qx > 0, hd = qy + 1 < lh, hu = qy > 0;
-    load_rec<C>(pack, pix, own);
-    load_rec<C>(pack, hr ? (uint64_t)pix + 1 : (uint64_t)pix, rr);
-    load_rec<C>(pack, hl ? (uint64_t)pix - 1 : (uint64_t)pix, rl);
-    load_rec<C>(pack, hd ? (uint64_t)pix + lw : (uint64_t)pix, rd);
-    load_rec<C>(pack, hu ? (uint64_t)pix - lw : (uint64_t)pix, ru);
     if (vis) {
         float inv = __builtin_amdgcn_rcpf(own[PL::count]);
 #pragma unroll
@@ -716,7 +731,7 @@ __device__ __forceinline__ void layer_work(const float* __restrict__ pack, uint3
 // kVisUnknown to test the point against the records here.
 constexpr uint32_t kVisUnknown = 0xffffffffu;
 
-template <int C, bool OPTS, int LN, typename Terms>
+template <int C, bool OPTS, int LN, bool UNI, typename Terms>
 __device__ __forceinline__ void point_view(const Cam& c, int L, float fa, bool spatial_all,
                                            const float* __restrict__ pack, bool live, float x, float y, float z,
                                            const float (&tau)[C], float (&dt)[C], float (&dp)[3], Terms& acc,
@@ -769,7 +784,7 @@ __device__ __forceinline__ void point_view(const Cam& c, int L, float fa, bool s
         layer_pixel_at(true, l, lw, lh, lbase, p.u0, p.v0, qx, qy, pix);
         const bool vis = (seen >> l) & 1u;
         float du = 0.f, dv = 0.f;
-        layer_work<C>(pack, pix, qx, qy, lw, lh, p.Z, fa, vis, tau, dt, du, dv);
+        layer_work<C, UNI>(pack, pix, qx, qy, lw, lh, p.Z, fa, vis, tau, dt, du, dv);
         const float s = 0.5f * layer_scale(l);
         gu = __fmaf_rn(du, s, gu);
         gv = __fmaf_rn(dv, s, gv);
@@ -937,8 +952,8 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
             bool any = false;
 #pragma unroll
             for (int k = 0; k < PPL; ++k)
-                point_view<C, OPTS, LN>(c0, L, fa, spatial_all, pack, live[k], px_[k], py_[k], pz_[k], tau[k],
-                                        dt[k], dp[k], lterms, any, o, ex[k], known[k]);
+                point_view<C, OPTS, LN, true>(c0, L, fa, spatial_all, pack, live[k], px_[k], py_[k], pz_[k],
+                                              tau[k], dt[k], dp[k], lterms, any, o, ex[k], known[k]);
         } else {
             for (int v = 0; v < V; ++v) {
                 const Cam cv = load_cam(views + v);
@@ -951,8 +966,8 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
                     const int64_t i = index(c, k);
                     const uint32_t kn = (use_vis && live[k]) ? (uint32_t)vis[(uint64_t)v * (uint64_t)n + (uint64_t)i]
                                                              : kVisUnknown;
-                    point_view<C, OPTS, LN>(cv, L, fa, spatial_all, pack, live[k], px_[k], py_[k], pz_[k], tau[k],
-                                            dt[k], dp[k], acc, any, o, ex[k], kn);
+                    point_view<C, OPTS, LN, false>(cv, L, fa, spatial_all, pack, live[k], px_[k], py_[k],
+                                                   pz_[k], tau[k], dt[k], dp[k], acc, any, o, ex[k], kn);
                 }
                 reduce_terms(acc, any, acc_lds + (wave * V + v) * 16, lane);
             }
