@@ -149,6 +149,66 @@ def atomic_sweep(ctx):
     return rows
 
 
+def multiview_leg(ctx, steps, warmup, n=30_000_000):
+    """The batched training step of the 16-view workload (30M points, C = 8
+    BF16 features, 1920x1080, L = 5, one fused launch per pass): forward with
+    the blend-set bits, then backward, timed over `steps` steps."""
+    import numpy as np
+    import torch
+    from paper_2110_06635_amd import adop, synth
+    s = synth.config4(n=n)
+    V, C = len(s.cams), s.c
+    dev = torch.device("cuda:0")
+    target = torch.from_numpy(synth.target_values(adop.views_layout(s.cams, s.layers)[0] * C)).to(dev)
+    raw, _ = synth.storage(s.feat, "bf16")
+    code = adop.DTYPES["bf16"]
+    pos = torch.from_numpy(s.pos).to(dev)
+    feat = torch.from_numpy(raw.view(np.int16)).to(dev).view(adop.TORCH_STORAGE[code])
+    scene = adop.Scene.prepare(ctx, pos, feat, code)
+    del pos, feat, raw
+    s.pos, s.feat = s.pos[:0], s.feat[:0]
+    frame = adop.Frame(s.cams, s.layers, C, dev)
+    ws = ctx.workspace(C, V, frame.pixels)
+    adop.render_forward(ctx, scene, frame.cams, s.layers, alpha=s.alpha, frame=frame, workspace=ws,
+                        record_visibility=True)
+    G = l1_grad(frame, target)
+    out = (torch.empty((scene.n, C), dtype=torch.float32, device=dev),
+           torch.empty((3, scene.n), dtype=torch.float32, device=dev),
+           torch.empty((V, 6), dtype=torch.float64, device=dev),
+           torch.empty((V, 9), dtype=torch.float64, device=dev))
+
+    def step():
+        adop.render_forward(ctx, scene, frame.cams, s.layers, alpha=s.alpha, frame=frame, workspace=ws,
+                            record_visibility=True)
+        adop.render_backward(ctx, scene, frame, G, alpha=s.alpha, out=out, workspace=ws)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.timing_read()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    kern = ctx.timing_read()
+    ctx.timing(False)
+    phi = float((out[0] != 0).any(dim=1).float().mean().item())
+    ab = algorithmic_bytes(scene.n, C, 2, phi, frame.pixels)   # points read once per fused pass
+    res = {"workload": s.name, "points": scene.n, "views": V, "channels": C, "feature_storage": "bf16",
+           "steps": steps, "warmup": warmup, "ms_per_step": round(ms, 4),
+           "value": scene.n * V / (ms * 1e-3), "unit": "point-views/s",
+           "step_frac_of_hbm_roofline": round(sum(ab.values()) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "kernels_ms": {k: round(v[0] / v[1], 4) for k, v in kern.items() if v[1]}}
+    del scene, frame, G, out, ws
+    torch.cuda.empty_cache()
+    return res
+
+
 def host_cpu():
     """Host CPU model name and logical CPU count."""
     model = ""
@@ -314,6 +374,9 @@ def main():
                     help="a second, saturating arrival rate (0: none)")
     ap.add_argument("--no-serve-leg", action="store_true",
                     help="skip the short serving leg of the default run")
+    ap.add_argument("--no-multiview-leg", action="store_true",
+                    help="skip the short 16-view leg of the default run")
+    ap.add_argument("--multiview-steps", type=int, default=5)
     ap.add_argument("--leg-requests", type=int, default=1500, help="measured requests per rate in the serving leg")
     ap.add_argument("--leg-warmup", type=int, default=100)
     ap.add_argument("--serve-batch", type=int, default=4)
@@ -472,10 +535,11 @@ def main():
     variants = {}
     for vd in [v for v in args.variants.split(",") if v and v != args.dtype]:
         log(f"timing variant {vd}")
-        rv = run(vd, max(3, args.steps // 2), 2, timing=False)
+        rv = run(vd, max(3, args.steps // 2), 2, timing=True)
         abv = algorithmic_bytes(n, C, rv["s"], rv["phi"], rv["pixels"])
         variants[vd] = {"value": n * V / (rv["ms"] * 1e-3), "ms_per_step": round(rv["ms"], 4),
-                        "step_frac_of_hbm_roofline": round(sum(abv.values()) / (rv["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                        "step_frac_of_hbm_roofline": round(sum(abv.values()) / (rv["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "kernels_ms": {k: round(v[0] / v[1], 4) for k, v in rv["kern"].items() if v[1]}}
     atomics = atomic_ceiling(ctx) if (args.workload == "gmm100m" and not options) else None
     cpu = None
     if not args.no_cpu and V == 1 and not options:
@@ -487,6 +551,10 @@ def main():
         serving = serving_leg(args.serve_points, args.leg_requests, args.leg_warmup,
                               [args.serve_rate] + ([args.serve_rate_high] if args.serve_rate_high > 0 else []),
                               max_batch=args.serve_batch, budget_gib=args.serve_budget_gib)
+    multiview = None
+    if args.workload == "gmm100m" and not options and not args.no_multiview_leg:
+        log("16-view leg: 30M points x 16 views, C = 8 BF16")
+        multiview = multiview_leg(ctx, args.multiview_steps, 2)
     line = {
         "metric": ("points/sec fwd+bwd at 100M pts 1080p (% HBM roofline); p99 render latency"
                    if args.workload == "gmm100m" else f"point-views/sec fwd+bwd ({args.workload})"),
@@ -518,6 +586,7 @@ def main():
         "preprocess": r["pre"],
         "precision_variants": variants,
         "serving": serving,
+        "multiview": multiview,
         "atomic_ceiling": atomics,
     }
     print(json.dumps(line), flush=True)
