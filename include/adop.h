@@ -59,6 +59,7 @@ typedef int32_t adop_dtype;
 #define ADOP_MAX_CHANNELS  16
 #define ADOP_MAX_VIEWS    256   /* per forward call */
 #define ADOP_MAX_VIEWS_BWD 32   /* per backward call */
+#define ADOP_MAX_SIZE   65536   /* camera width and height (and a frame below 2^31 pixels) */
 
 /* render flags */
 #define ADOP_FLAG_SPATIAL_ALL 1u  /* spatial gradient for every in-bounds point,

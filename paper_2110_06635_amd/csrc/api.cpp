@@ -122,6 +122,8 @@ adop_status check_cameras(adop_context* ctx, const adop_camera* cams, int32_t V,
     for (int v = 0; v < V; ++v) {
         const adop_camera& c = cams[v];
         if (c.width < 1 || c.height < 1) return fail(ctx, ADOP_E_INVALID, "camera %d: size %dx%d", v, c.width, c.height);
+        if (c.width > ADOP_MAX_SIZE || c.height > ADOP_MAX_SIZE)
+            return fail(ctx, ADOP_E_UNSUPPORTED, "camera %d: size %dx%d above %d", v, c.width, c.height, ADOP_MAX_SIZE);
         if ((c.width >> (L - 1)) < 1 || (c.height >> (L - 1)) < 1)
             return fail(ctx, ADOP_E_INVALID, "camera %d: %dx%d too small for %d layers", v, c.width, c.height, L);
         if (!(c.znear >= 0.0f)) return fail(ctx, ADOP_E_INVALID, "camera %d: znear must be >= 0", v);

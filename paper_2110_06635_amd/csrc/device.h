@@ -454,40 +454,72 @@ __device__ __forceinline__ float ld_nt(const float* p) { return __builtin_nontem
 __device__ __forceinline__ int32_t ld_nt(const int32_t* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ void st_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
 
-// Load the C features of point i (row-major [n][C]) widened to FP32.
+// A point's features as loaded: the raw 32-bit words of its row (one vector
+// load per 16 or 8 bytes when the row allows it, else one element per word).
+// Prefetches keep the raw words and widen them when the point is processed:
+// a conversion right after the load would make the wave wait for it there.
 template <int C, typename S>
-__device__ __forceinline__ void load_feat(const void* feat, int64_t i, float (&f)[C]) {
+struct FeatRaw {
+    static constexpr int bytes = C * S::bytes;
+    static constexpr bool vec = bytes % 8 == 0;
+    static constexpr int words = vec ? bytes / 4 : C;
+    uint32_t w[words];
+};
+
+template <int C, typename S>
+__device__ __forceinline__ void load_feat_raw(const void* feat, int64_t i, FeatRaw<C, S>& r) {
     using T = typename S::T;
     const T* p = reinterpret_cast<const T*>(feat) + i * C;
     constexpr int bytes = C * S::bytes;
     if constexpr (bytes % 16 == 0) {
         const vu4* q = reinterpret_cast<const vu4*>(p);
-        T tmp[C];
 #pragma unroll
         for (int k = 0; k < bytes / 16; ++k) {
             vu4 v = __builtin_nontemporal_load(q + k);
-            reinterpret_cast<uint32_t*>(tmp)[4 * k] = v.x;
-            reinterpret_cast<uint32_t*>(tmp)[4 * k + 1] = v.y;
-            reinterpret_cast<uint32_t*>(tmp)[4 * k + 2] = v.z;
-            reinterpret_cast<uint32_t*>(tmp)[4 * k + 3] = v.w;
+            r.w[4 * k] = v.x;
+            r.w[4 * k + 1] = v.y;
+            r.w[4 * k + 2] = v.z;
+            r.w[4 * k + 3] = v.w;
         }
-#pragma unroll
-        for (int c = 0; c < C; ++c) f[c] = widen<S>(tmp[c]);
     } else if constexpr (bytes % 8 == 0) {
         const vu2* q = reinterpret_cast<const vu2*>(p);
-        T tmp[C];
 #pragma unroll
         for (int k = 0; k < bytes / 8; ++k) {
             vu2 v = __builtin_nontemporal_load(q + k);
-            reinterpret_cast<uint32_t*>(tmp)[2 * k] = v.x;
-            reinterpret_cast<uint32_t*>(tmp)[2 * k + 1] = v.y;
+            r.w[2 * k] = v.x;
+            r.w[2 * k + 1] = v.y;
         }
-#pragma unroll
-        for (int c = 0; c < C; ++c) f[c] = widen<S>(tmp[c]);
     } else {
 #pragma unroll
-        for (int c = 0; c < C; ++c) f[c] = widen<S>(p[c]);
+        for (int c = 0; c < C; ++c) {
+            if constexpr (S::bytes == 4)
+                r.w[c] = __float_as_uint(p[c]);
+            else
+                r.w[c] = (uint32_t)p[c];
+        }
     }
+}
+
+template <int C, typename S>
+__device__ __forceinline__ void widen_feat(const FeatRaw<C, S>& r, float (&f)[C]) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        if constexpr (S::bytes == 4) {
+            f[c] = __uint_as_float(r.w[c]);
+        } else if constexpr (FeatRaw<C, S>::vec) {
+            f[c] = widen<S>((uint16_t)(r.w[c >> 1] >> (16 * (c & 1))));   // little-endian pairs
+        } else {
+            f[c] = widen<S>((uint16_t)r.w[c]);
+        }
+    }
+}
+
+// Load the C features of point i (row-major [n][C]) widened to FP32.
+template <int C, typename S>
+__device__ __forceinline__ void load_feat(const void* feat, int64_t i, float (&f)[C]) {
+    FeatRaw<C, S> r;
+    load_feat_raw<C, S>(feat, i, r);
+    widen_feat<C, S>(r, f);
 }
 
 template <int C>

@@ -465,9 +465,10 @@ __global__ void __launch_bounds__(256) k_accum(const float* __restrict__ xs, con
         return (vrow != nullptr && i < n) ? (uint32_t)vrow[i] : 0xffu;
     };
     // the next chunk's points are loaded while the current one is processed
-    float nx = 0.f, ny = 0.f, nz = 0.f, nf[C];
+    float nx = 0.f, ny = 0.f, nz = 0.f;
+    FeatRaw<C, S> nf;
 #pragma unroll
-    for (int ch = 0; ch < C; ++ch) nf[ch] = 0.f;
+    for (int k = 0; k < FeatRaw<C, S>::words; ++k) nf.w[k] = 0u;
     bool nlive = false;
     uint32_t ncand = 0xffu, ncand2 = 0xffu;   // candidates of chunks c + 1 and c + 2
     PointExtra ne;
@@ -478,7 +479,7 @@ __global__ void __launch_bounds__(256) k_accum(const float* __restrict__ xs, con
             nx = ld_nt(xs + i);
             ny = ld_nt(ys + i);
             nz = ld_nt(zs + i);
-            load_feat<C, S>(feat, i, nf);
+            load_feat_raw<C, S>(feat, i, nf);
             if (OPTS) load_extra(o, i, ne);
         }
     };
@@ -491,9 +492,7 @@ __global__ void __launch_bounds__(256) k_accum(const float* __restrict__ xs, con
         const bool live = nlive;
         const uint32_t cand = ncand;
         const float x = nx, y = ny, z = nz;
-        float f[C];
-#pragma unroll
-        for (int ch = 0; ch < C; ++ch) f[ch] = nf[ch];
+        const FeatRaw<C, S> fr = nf;
         const PointExtra e = ne;
         ncand = ncand2;
         if (c + 1 < m.c1) fetch(c + 1);
@@ -503,6 +502,8 @@ __global__ void __launch_bounds__(256) k_accum(const float* __restrict__ xs, con
             if (vrow != nullptr && live) vrow[i] = 0;
             continue;
         }
+        float f[C];
+        widen_feat<C, S>(fr, f);
         if (OPTS && (o.flags & kOptLog)) {
 #pragma unroll
             for (int ch = 0; ch < C; ++ch) f[ch] = expf(f[ch]);
@@ -880,7 +881,8 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
     // positions and features one chunk ahead, only for points with bits
     // (a point that blends nowhere costs its bit load and its zero stores).
     uint32_t kn1[PPL], kn2[PPL];   // bits of chunks c + 1 and c + 2
-    float nx[PPL], ny[PPL], nz[PPL], nf[PPL][C];
+    float nx[PPL], ny[PPL], nz[PPL];
+    FeatRaw<C, S> nf[PPL];
     PointExtra nex[PPL];
     auto bits = [&](int64_t cc, int k) -> uint32_t {
         const int64_t i = index(cc, k);
@@ -894,7 +896,7 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
                 nx[k] = ld_nt(xs + i);
                 ny[k] = ld_nt(ys + i);
                 nz[k] = ld_nt(zs + i);
-                load_feat<C, S>(feat, i, nf[k]);
+                load_feat_raw<C, S>(feat, i, nf[k]);
                 if (OPTS) load_extra(o, i, nex[k]);
             }
         }
@@ -904,7 +906,7 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
         kn1[k] = kn2[k] = kVisUnknown;
         nx[k] = ny[k] = nz[k] = 0.f;
 #pragma unroll
-        for (int ch = 0; ch < C; ++ch) nf[k][ch] = 0.f;
+        for (int q = 0; q < FeatRaw<C, S>::words; ++q) nf[k].w[q] = 0u;
     }
     if (m.c0 < m.c1) {
 #pragma unroll
@@ -929,11 +931,9 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
             py_[k] = ny[k];
             pz_[k] = nz[k];
             ex[k] = nex[k];
+            widen_feat<C, S>(nf[k], tau[k]);
 #pragma unroll
-            for (int ch = 0; ch < C; ++ch) {
-                tau[k][ch] = nf[k][ch];
-                dt[k][ch] = 0.f;
-            }
+            for (int ch = 0; ch < C; ++ch) dt[k][ch] = 0.f;
             dp[k][0] = dp[k][1] = dp[k][2] = 0.f;
             kn1[k] = kn2[k];
         }

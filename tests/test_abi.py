@@ -65,10 +65,15 @@ def test_views_layout(A):
     assert total5 == 2_762_040
 
 
-@pytest.mark.parametrize("w,h,L", [(1, 5, 2), (8, 8, 9), (0, 4, 1), (16, 16, 0)])
+@pytest.mark.parametrize("w,h,L", [(1, 5, 2), (8, 8, 9), (0, 4, 1), (16, 16, 0), (65537, 2, 1), (4, 65537, 1)])
 def test_views_layout_rejects(A, w, h, L):
     with pytest.raises(A.AdopError):
         A.views_layout([_cam(w, h)], L)
+
+
+def test_views_layout_largest_size(A):
+    total, _ = A.views_layout([_cam(65536, 2)], 1)
+    assert total == 131072
 
 
 def test_workspace_bytes(A):
