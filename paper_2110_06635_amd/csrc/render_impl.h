@@ -68,7 +68,8 @@ __global__ void __launch_bounds__(256) k_clear(uint64_t* __restrict__ keys, int3
 // rounding): the bits are a superset of the layers where it blends.
 template <bool OPTS, int LN>
 __device__ __forceinline__ uint32_t depth_point(const Cam& c, int L, float fa, bool live, float x, float y, float z,
-                                                uint32_t oi, const PointOpts& o, const PointExtra& e,
+                                                const int32_t* __restrict__ orig, uint64_t i, uint32_t& oi,
+                                                bool& have_oi, const PointOpts& o, const PointExtra& e,
                                                 uint64_t* __restrict__ keys) {
     Proj p = project(c, x, y, z);
     bool ok = live && p.ok;
@@ -77,10 +78,15 @@ __device__ __forceinline__ uint32_t depth_point(const Cam& c, int L, float fa, b
         ok = ok && normal_kept(o, c, p, e);
         if (ok) lmask = discard_mask(o, c, p, e, L);
     }
-    uint64_t key = ((uint64_t)__float_as_uint(p.Z) << 32) | oi;
+    // Only the depth word (the high half) of each current key is read: the
+    // candidate test needs nothing else, and a point goes on to the atomic
+    // when its depth is at most the front's (an equal depth may still win
+    // the tie on its index; the 64-bit atomic minimum decides).
+    const uint32_t* keys_hi = reinterpret_cast<const uint32_t*>(keys) + 1;
+    const uint32_t zb = __float_as_uint(p.Z);
     uint32_t pix[Layers<LN>::max];
     bool in[Layers<LN>::max];
-    uint64_t cur[Layers<LN>::max];
+    uint32_t cur[Layers<LN>::max];
 #pragma unroll
     for (int l = 0; l < Layers<LN>::max; ++l) {
         pix[l] = 0;
@@ -89,24 +95,34 @@ __device__ __forceinline__ uint32_t depth_point(const Cam& c, int L, float fa, b
         if (Layers<LN>::has(l, L)) {
             int px = 0, py = 0;
             in[l] = layer_pixel(c, ok, l, p.u0, p.v0, px, py, pix[l]) && ((lmask >> l) & 1u);
-            cur[l] = load_relaxed_u64(keys + pix[l]);   // pix is valid for every lane
+            cur[l] = load_relaxed_u32(keys_hi + 2 * (uint64_t)pix[l]);   // pix is valid for every lane
         }
     }
     // keep the L gathers in flight together: nothing that uses them is
     // scheduled between them
     __builtin_amdgcn_sched_barrier(0);
     uint32_t cand = 0;
+    bool any = false;
 #pragma unroll
     for (int l = 0; l < Layers<LN>::max; ++l) {
         if (!Layers<LN>::has(l, L)) break;
-        // an empty key reads as NaN depth: the point stays a candidate
-        const float zr = __uint_as_float(__builtin_bit_cast(vu2, cur[l]).y);
+        // an empty key reads as NaN depth: the point stays a candidate; a
+        // visible depth is positive, so its bits order as the values do
+        const float zr = __uint_as_float(cur[l]);
         cand |= (uint32_t)(in[l] && !(p.Z > __fmul_rn(zr, fa))) << l;
+        any |= in[l] && zb <= cur[l];
     }
+    if (ballot(any) == 0) return cand;
+    // the original index is needed only for the atomics' keys
+    if (!have_oi) {
+        oi = live ? (uint32_t)ld_nt(orig + i) : 0u;
+        have_oi = true;
+    }
+    const uint64_t key = ((uint64_t)zb << 32) | oi;
 #pragma unroll
     for (int l = 0; l < Layers<LN>::max; ++l) {
         if (!Layers<LN>::has(l, L)) break;
-        bool want = in[l] && key < cur[l];
+        bool want = in[l] && zb <= cur[l];
         uint64_t m = ballot(want);
         if (m == 0) continue;
         int leader = __builtin_ctzll(m);
@@ -133,7 +149,7 @@ static_assert(kDepthSample >= 2, "sample stride");
 // cand (optional, [V][n]): the candidate layers of every point and view,
 // read and overwritten by the accumulation pass.
 template <bool SINGLE, bool OPTS, int LN>
-__global__ void __launch_bounds__(256) k_depth(const float* __restrict__ xs, const float* __restrict__ ys,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_depth(const float* __restrict__ xs, const float* __restrict__ ys,
                                                const float* __restrict__ zs, const int32_t* __restrict__ orig,
                                                int64_t n, const ViewRec* __restrict__ views, int V, int L,
                                                float fa, PointOpts o, uint64_t* __restrict__ keys,
@@ -141,6 +157,8 @@ __global__ void __launch_bounds__(256) k_depth(const float* __restrict__ xs, con
     const Cam c0 = load_cam(views);
     RangeMap m = range_map(n, kBlock);
     // the next chunk's points are loaded while the current one is processed
+    // (one view: the original index is loaded only by waves that reach an
+    // atomic; several views, where nearly every wave does, prefetch it)
     float nx = 0.f, ny = 0.f, nz = 0.f;
     uint32_t noi = 0;
     bool nlive = false;
@@ -152,7 +170,7 @@ __global__ void __launch_bounds__(256) k_depth(const float* __restrict__ xs, con
             nx = ld_nt(xs + i);
             ny = ld_nt(ys + i);
             nz = ld_nt(zs + i);
-            noi = (uint32_t)ld_nt(orig + i);
+            if (!SINGLE) noi = (uint32_t)ld_nt(orig + i);
             if (OPTS) load_extra(o, i, ne);
         }
     };
@@ -174,16 +192,19 @@ __global__ void __launch_bounds__(256) k_depth(const float* __restrict__ xs, con
         const int64_t c = chunk_at(j);
         const bool live = nlive;
         const float x = nx, y = ny, z = nz;
-        const uint32_t oi = noi;
+        const uint32_t oi0 = noi;
         const PointExtra e = ne;
         if (j + 1 < len) fetch(chunk_at(j + 1));
         const uint64_t i = (uint64_t)(c * kBlock + threadIdx.x);
+        uint32_t oi = oi0;
+        bool have_oi = !SINGLE;
         if (SINGLE) {
-            const uint32_t cm = depth_point<OPTS, LN>(c0, L, fa, live, x, y, z, oi, o, e, keys);
+            const uint32_t cm = depth_point<OPTS, LN>(c0, L, fa, live, x, y, z, orig, i, oi, have_oi, o, e, keys);
             if (cand != nullptr && live) cand[i] = (uint8_t)cm;
         } else {
             for (int v = 0; v < V; ++v) {
-                const uint32_t cm = depth_point<OPTS, LN>(load_cam(views + v), L, fa, live, x, y, z, oi, o, e, keys);
+                const uint32_t cm = depth_point<OPTS, LN>(load_cam(views + v), L, fa, live, x, y, z, orig, i, oi,
+                                                          have_oi, o, e, keys);
                 if (cand != nullptr && live) cand[(uint64_t)v * (uint64_t)n + i] = (uint8_t)cm;
             }
         }
