@@ -6,31 +6,37 @@
 // Forward (three passes over the points, as in "Implementation Details"):
 //   k_clear      keys := empty, counts := 0, sums := 0
 //   k_depth      project every point into every view and layer, 64-bit
-//                atomic minimum of (depth bits << 32 | original index)
-//   k_accum      fuzzy depth test z <= (1+alpha) min_z (Eq. depthtest),
-//                FP32 sums of the features and an integer count; optionally
-//                each point's blend-set bits (one byte per point and view)
-//   k_normalize  mean of the blend set or the background (Eq. blend)
+//                atomic minimum of (depth bits << 32 | original index);
+//                optionally marks each point's candidate layers (those where
+//                its depth is within (1+alpha) of the front it read)
+//   k_accum      fuzzy depth test z <= (1+alpha) min_z (Eq. depthtest) for
+//                the candidates, FP32 sums of the features and an integer
+//                count; optionally each point's blend-set bits (one byte per
+//                point and view)
+//   k_normalize  mean of the blend set, or for an empty pixel the constant
+//                background or the environment map's sample (Eq. blend)
 // Backward:
 //   k_pack       per-pixel record {G, <G,I>, min_z, (1+alpha) min_z, n}
 //   k_backward   re-render every point (the blend sets are not stored), or
 //                take the forward's blend-set bits and skip the points
-//                without any; feature gradient, approximate spatial gradient (Eqs. induce,
-//                gradp, spatialderiv), chain to positions, pose (Eq. tangent)
-//                and intrinsics; per-point terms in FP32, pose/intrinsics
-//                sums in FP64 with a fixed reduction order
+//                without any; feature gradient, approximate spatial gradient
+//                (Eqs. induce, gradp, spatialderiv), chain to positions, pose
+//                (Eq. tangent) and intrinsics; every per-point pose/intrinsics
+//                term widened to FP64 before it is added, sums in a fixed order
+//   k_env_grad   the environment map's gradient from the empty pixels
 //   k_reduce_slices, k_reduce   fixed-order FP64 sum of the per-workgroup
 //                partials (slices of workgroups, then the slices)
 //
 // Every workgroup of a point kernel owns one contiguous range of the
 // Morton-ordered points (a compact region of space), so the 64 points of a
 // wave usually land in one or a few pixels per layer.  The depth pass tests
-// each point against the pixel's current key and combines the lanes that
+// each point against the pixel's current front and combines the lanes that
 // would lower a key with a wave minimum (one pixel) or segmented minima over
 // runs of equal pixels; the accumulation pass combines passing lanes with a
 // wave sum (one pixel) into a per-wave register cache of pixel sums, or with
 // segmented sums over runs, in front of a workgroup table in LDS and the
-// global atomics.
+// channel-last global sums (one L2 request per update: C lanes add its C
+// channels in one instruction).
 #include <type_traits>
 #include "device.h"
 #include "launch.h"
