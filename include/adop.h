@@ -417,9 +417,11 @@ const char* adop_timing_kernel_name(int32_t kernel);
 /* Capture the forward pass for V cameras of fixed sizes into a HIP graph
  * bound to the given scene, frame and workspace.  The graph holds kernels
  * only; adop_forward_graph_launch stages new cameras (same widths and
- * heights as `cams`) into the workspace and replays it.  Launches of one
- * graph are serialised: a launch waits until the previous launch's camera
- * copy has been consumed. */
+ * heights as `cams`) into the workspace and replays it.  The cameras go
+ * through a ring of four pinned staging slots: a launch blocks the host only
+ * while the copy of four launches earlier is still pending.  The view
+ * records, frame and workspace are shared by all launches of one graph, so
+ * its launches must be ordered on one stream (or by the caller). */
 adop_status adop_forward_graph_create(adop_context* ctx, const adop_scene* scene,
                                       const adop_camera* cams, int32_t V,
                                       const adop_render_params* params,

@@ -77,13 +77,18 @@ struct adop_context {
     hipError_t scratch_error = hipSuccess;
 };
 
+// Camera staging of a captured graph: a ring of pinned slots, each reused
+// only after the copy that last read it has completed.
+constexpr int kGraphStaging = 4;
+
 struct adop_graph {
     adop_context* ctx = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    unsigned char* pinned = nullptr;
-    hipEvent_t ev = nullptr;
-    bool launched = false;
+    unsigned char* pinned = nullptr;           // kGraphStaging slots of V view records
+    hipEvent_t ev[kGraphStaging] = {};
+    bool used[kGraphStaging] = {};
+    int64_t launches = 0;
     int V = 0;
     int layers = 0;
     std::vector<int32_t> wh;
@@ -828,10 +833,12 @@ adop_status adop_forward_graph_create(adop_context* ctx, const adop_scene* scene
         adop_graph_destroy(g);
         return st;
     };
-    if ((e = hipHostMalloc((void**)&g->pinned, kSlotBytes, hipHostMallocDefault)) != hipSuccess)
+    if ((e = hipHostMalloc((void**)&g->pinned, (size_t)kGraphStaging * V * sizeof(ViewRec), hipHostMallocDefault)) !=
+        hipSuccess)
         return cleanup(hip_fail(ctx, e, "hipHostMalloc"));
-    if ((e = hipEventCreateWithFlags(&g->ev, hipEventDisableTiming)) != hipSuccess)
-        return cleanup(hip_fail(ctx, e, "hipEventCreate"));
+    for (int k = 0; k < kGraphStaging; ++k)
+        if ((e = hipEventCreateWithFlags(&g->ev[k], hipEventDisableTiming)) != hipSuccess)
+            return cleanup(hip_fail(ctx, e, "hipEventCreate"));
     if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess)
         return cleanup(hip_fail(ctx, e, "hipStreamCreate"));
     adop::FwdArgs a = fwd_args(ctx, scene, cams, V, params, frame, workspace, total);
@@ -864,24 +871,31 @@ adop_status adop_forward_graph_launch(adop_graph* g, const adop_camera* cams, vo
         if (cams[v].width != g->wh[2 * v] || cams[v].height != g->wh[2 * v + 1])
             return fail(ctx, ADOP_E_INVALID, "camera %d size differs from the captured graph", v);
     hipError_t e;
-    if (g->launched && (e = hipEventSynchronize(g->ev)) != hipSuccess) return hip_fail(ctx, e, "hipEventSynchronize");
+    const int k = (int)(g->launches % kGraphStaging);
+    // the slot's previous copy (kGraphStaging launches ago) must have read it
+    if (g->used[k] && (e = hipEventSynchronize(g->ev[k])) != hipSuccess)
+        return hip_fail(ctx, e, "hipEventSynchronize");
     hipStream_t st = (hipStream_t)stream;
-    make_views(cams, g->V, g->layers, reinterpret_cast<ViewRec*>(g->pinned));
-    if ((e = hipMemcpyAsync(g->views_dev, g->pinned, (size_t)g->V * sizeof(ViewRec), hipMemcpyHostToDevice, st)) !=
+    ViewRec* host = reinterpret_cast<ViewRec*>(g->pinned) + (size_t)k * g->V;
+    make_views(cams, g->V, g->layers, host);
+    if ((e = hipMemcpyAsync(g->views_dev, host, (size_t)g->V * sizeof(ViewRec), hipMemcpyHostToDevice, st)) !=
         hipSuccess)
         return hip_fail(ctx, e, "hipMemcpyAsync(views)");
-    if ((e = hipEventRecord(g->ev, st)) != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
-    g->launched = true;
+    if ((e = hipEventRecord(g->ev[k], st)) != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
+    g->used[k] = true;
+    ++g->launches;
     if ((e = hipGraphLaunch(g->exec, st)) != hipSuccess) return hip_fail(ctx, e, "hipGraphLaunch");
     return ADOP_OK;
 }
 
 void adop_graph_destroy(adop_graph* g) {
     if (!g) return;
-    if (g->launched && g->ev) (void)hipEventSynchronize(g->ev);
+    for (int k = 0; k < kGraphStaging; ++k)
+        if (g->used[k] && g->ev[k]) (void)hipEventSynchronize(g->ev[k]);
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
-    if (g->ev) (void)hipEventDestroy(g->ev);
+    for (int k = 0; k < kGraphStaging; ++k)
+        if (g->ev[k]) (void)hipEventDestroy(g->ev[k]);
     if (g->pinned) (void)hipHostFree(g->pinned);
     delete g;
 }
