@@ -905,8 +905,9 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
         return cc * kBlock * PPL + (int64_t)wave * kWave * PPL + (int64_t)k * kWave + lane;
     };
     // One view: the blend-set bits are loaded two chunks ahead and the
-    // positions and features one chunk ahead, only for points with bits
-    // (a point that blends nowhere costs its bit load and its zero stores).
+    // positions and features one chunk ahead (after the current chunk's
+    // gathers), only for points with bits (a point that blends nowhere costs
+    // its bit load and its zero stores).
     uint32_t kn1[PPL], kn2[PPL];   // bits of chunks c + 1 and c + 2
     float nx[PPL], ny[PPL], nz[PPL];
     FeatRaw<C, S> nf[PPL];
@@ -964,7 +965,6 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
             dp[k][0] = dp[k][1] = dp[k][2] = 0.f;
             kn1[k] = kn2[k];
         }
-        if (c + 1 < m.c1) fetch(c + 1);
         if (c + 2 < m.c1) {
 #pragma unroll
             for (int k = 0; k < PPL; ++k) kn2[k] = bits(c + 2, k);
@@ -999,6 +999,10 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
                 reduce_terms(acc, any, acc_lds + (wave * V + v) * 16, lane);
             }
         }
+        // The next chunk's positions and features are requested only now:
+        // a wave's loads complete in issue order, so loads issued before this
+        // chunk's record gathers would hold up every wait on those gathers.
+        if (c + 1 < m.c1) fetch(c + 1);
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
             if (!live[k]) continue;
