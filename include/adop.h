@@ -44,7 +44,7 @@ extern "C" {
 typedef int32_t adop_status;
 #define ADOP_OK             0
 #define ADOP_E_INVALID      1   /* an argument is out of range or inconsistent */
-#define ADOP_E_UNSUPPORTED  2   /* valid request this build does not implement */
+#define ADOP_E_UNSUPPORTED  2   /* valid request the library does not implement */
 #define ADOP_E_WORKSPACE    3   /* workspace smaller than adop_workspace_bytes */
 #define ADOP_E_DEVICE       4   /* HIP runtime error (text in adop_last_error) */
 #define ADOP_E_STATE        5   /* call out of order (e.g. graph in use) */
