@@ -866,15 +866,32 @@ struct RegTerms {
     }
 };
 
-// FP64 sums of the 15 terms over the wave (fixed DPP order); lane 0 adds
-// them to the wave's own LDS slot, so the order is fixed for a fixed grid.
-__device__ __forceinline__ void reduce_terms(const RegTerms& acc, bool any, double* __restrict__ slot, int lane) {
+// FP64 sums of the 15 terms over the wave, transposed through LDS: every
+// lane writes its terms to the wave's [15][64] scratch, lane 4t + q adds
+// entries 16q .. 16q + 15 of term t in order, the quarters are combined as
+// (q0 + q1) + (q2 + q3), and lane 4t adds term t's sum to the wave's own
+// slot.  The order is fixed, so for a fixed grid the result is too.  (The
+// wave's LDS operations complete in issue order, so the reads see every
+// lane's writes; the next call's writes follow these reads.)
+__device__ __forceinline__ void reduce_terms(const RegTerms& acc, bool any, double* __restrict__ slot, int lane,
+                                             double* __restrict__ scratch) {
     if (ballot(any) == 0) return;
 #pragma unroll
-    for (int t = 0; t < 15; ++t) {
-        double s = wave_sum_f64(acc.v[t]);
-        if (lane == 0) slot[t] += s;
+    for (int t = 0; t < 15; ++t) scratch[t * kWave + lane] = acc.v[t];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int t = lane >> 2, q = lane & 3;
+    double s = 0.0;
+    if (lane < 60) {
+        const double* col = scratch + t * kWave + q * 16;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) s += col[k];
     }
+    s += __shfl_xor(s, 1);
+    s += __shfl_xor(s, 2);
+    if (lane < 60 && q == 0) slot[t] += s;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 }
 
 template <int C, typename S, int PPL, bool SINGLE, bool OPTS, int LN>
@@ -886,7 +903,7 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
                                                   float* __restrict__ dfeat, float* __restrict__ dpos,
                                                   double* __restrict__ partials, const uint8_t* __restrict__ vis) {
     // one view: [15][256] per-lane FP64 slots; several views: [4 waves][V][16]
-    // per-wave FP64 sums (dynamic LDS)
+    // per-wave FP64 sums, then [4 waves][15][64] reduction scratch (dynamic LDS)
     extern __shared__ double acc_lds[];
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
@@ -996,7 +1013,8 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
                     point_view<C, OPTS, LN, false>(cv, L, fa, spatial_all, pack, live[k], px_[k], py_[k],
                                                    pz_[k], tau[k], dt[k], dp[k], acc, any, o, ex[k], kn);
                 }
-                reduce_terms(acc, any, acc_lds + (wave * V + v) * 16, lane);
+                reduce_terms(acc, any, acc_lds + (wave * V + v) * 16, lane,
+                             acc_lds + 4 * V * 16 + wave * 15 * kWave);
             }
         }
         // The next chunk's positions and features are requested only now:
@@ -1215,9 +1233,12 @@ static hipError_t forward_impl(const FwdArgs& a, hipStream_t st) {
 template <int C, typename S, bool SINGLE, bool OPTS, int LN>
 static unsigned backward_pass(const BwdArgs& a, hipStream_t st) {
     constexpr int PPL = bwd_points_per_lane<SINGLE>();
-    const size_t lds = SINGLE ? (size_t)15 * kBlock * sizeof(double) : (size_t)4 * a.V * 16 * sizeof(double);
+    // several views: the per-wave view sums and the reduction scratch
+    constexpr size_t kScratch = (size_t)4 * 15 * kWave * sizeof(double);
+    const size_t lds = SINGLE ? (size_t)15 * kBlock * sizeof(double)
+                              : (size_t)4 * a.V * 16 * sizeof(double) + kScratch;
     static const int occ = resident(k_backward<C, S, PPL, SINGLE, OPTS, LN>,
-                                    SINGLE ? lds : (size_t)4 * kMaxViewsBwd * 16 * sizeof(double));
+                                    SINGLE ? lds : (size_t)4 * kMaxViewsBwd * 16 * sizeof(double) + kScratch);
     unsigned g = persistent_grid(a.n, (int64_t)kBlock * PPL, a.cus, occ, a.groups);
     g = std::min<unsigned>(range_grid(a.n, kBackwardRange, g), (unsigned)a.groups / kXcds * kXcds);
     a.timer.mark(kKBackward, 0, st);
