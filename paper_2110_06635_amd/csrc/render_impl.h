@@ -169,9 +169,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
     uint32_t noi = 0;
     bool nlive = false;
     PointExtra ne;
-    auto fetch = [&](int64_t c) {
-        int64_t i = c * kBlock + threadIdx.x;
-        nlive = i < n;
+    // chunk and point numbers fit 32 bits (n < 2^31, so c * kBlock + 255 < 2^32)
+    auto fetch = [&](uint32_t c) {
+        const uint32_t i = c * (uint32_t)kBlock + threadIdx.x;
+        nlive = (int64_t)i < n;
         if (nlive) {
             nx = ld_nt(xs + i);
             ny = ld_nt(ys + i);
@@ -186,22 +187,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
     // the keys hold nearly the final fronts, so the later points mostly find
     // themselves behind them: fewer atomics here and fewer candidates for the
     // accumulation pass.
-    const int64_t len = m.c1 - m.c0;
-    const int64_t q = (len + kDepthSample - 1) / kDepthSample;
-    auto chunk_at = [&](int64_t j) -> int64_t {
-        if (j < q) return m.c0 + j * kDepthSample;
+    const uint32_t cs0 = (uint32_t)m.c0;
+    const uint32_t len = (uint32_t)(m.c1 - m.c0);
+    constexpr uint32_t kS = (uint32_t)kDepthSample;
+    const uint32_t q = (len + kS - 1) / kS;
+    auto chunk_at = [&](uint32_t j) -> uint32_t {
+        if (j < q) return cs0 + j * kS;
         j -= q;   // j-th chunk whose offset is not a multiple of kDepthSample
-        return m.c0 + j + j / (kDepthSample - 1) + 1;
+        return cs0 + j + j / (kS - 1) + 1;
     };
     if (len > 0) fetch(chunk_at(0));
-    for (int64_t j = 0; j < len; ++j) {
-        const int64_t c = chunk_at(j);
+    for (uint32_t j = 0; j < len; ++j) {
+        const uint32_t c = chunk_at(j);
         const bool live = nlive;
         const float x = nx, y = ny, z = nz;
         const uint32_t oi0 = noi;
         const PointExtra e = ne;
         if (j + 1 < len) fetch(chunk_at(j + 1));
-        const uint64_t i = (uint64_t)(c * kBlock + threadIdx.x);
+        const uint64_t i = (uint64_t)(c * (uint32_t)kBlock + threadIdx.x);
         uint32_t oi = oi0;
         bool have_oi = !SINGLE;
         if (SINGLE) {
@@ -923,8 +926,11 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
     LdsTerms lterms{acc_lds + threadIdx.x};
 
     RangeMap m = range_map(n, (int64_t)kBlock * PPL);
-    auto index = [&](int64_t cc, int k) -> int64_t {
-        return cc * kBlock * PPL + (int64_t)wave * kWave * PPL + (int64_t)k * kWave + lane;
+    // chunk and point numbers fit 32 bits (n < 2^31, so the last chunk's
+    // indices stay below 2^32)
+    const uint32_t cb0 = (uint32_t)m.c0, cb1 = (uint32_t)m.c1;
+    auto index = [&](uint32_t cc, int k) -> uint32_t {
+        return cc * (uint32_t)(kBlock * PPL) + (uint32_t)(wave * kWave * PPL + k * kWave + lane);
     };
     // One view: the blend-set bits are loaded two chunks ahead and the
     // positions and features one chunk ahead (after the current chunk's
@@ -934,15 +940,15 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
     float nx[PPL], ny[PPL], nz[PPL];
     FeatRaw<C, S> nf[PPL];
     PointExtra nex[PPL];
-    auto bits = [&](int64_t cc, int k) -> uint32_t {
-        const int64_t i = index(cc, k);
-        return (SINGLE && use_vis && i < n) ? (uint32_t)vis[i] : kVisUnknown;
+    auto bits = [&](uint32_t cc, int k) -> uint32_t {
+        const uint32_t i = index(cc, k);
+        return (SINGLE && use_vis && (int64_t)i < n) ? (uint32_t)vis[i] : kVisUnknown;
     };
-    auto fetch = [&](int64_t cc) {
+    auto fetch = [&](uint32_t cc) {
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
-            const int64_t i = index(cc, k);
-            if (i < n && kn1[k] != 0) {
+            const uint32_t i = index(cc, k);
+            if ((int64_t)i < n && kn1[k] != 0) {
                 nx[k] = ld_nt(xs + i);
                 ny[k] = ld_nt(ys + i);
                 nz[k] = ld_nt(zs + i);
@@ -958,16 +964,16 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
 #pragma unroll
         for (int q = 0; q < FeatRaw<C, S>::words; ++q) nf[k].w[q] = 0u;
     }
-    if (m.c0 < m.c1) {
+    if (cb0 < cb1) {
 #pragma unroll
-        for (int k = 0; k < PPL; ++k) kn1[k] = bits(m.c0, k);
-        fetch(m.c0);
+        for (int k = 0; k < PPL; ++k) kn1[k] = bits(cb0, k);
+        fetch(cb0);
     }
-    if (m.c0 + 1 < m.c1) {
+    if (cb0 + 1 < cb1) {
 #pragma unroll
-        for (int k = 0; k < PPL; ++k) kn2[k] = bits(m.c0 + 1, k);
+        for (int k = 0; k < PPL; ++k) kn2[k] = bits(cb0 + 1, k);
     }
-    for (int64_t c = m.c0; c < m.c1; ++c) {
+    for (uint32_t c = cb0; c < cb1; ++c) {
         float px_[PPL], py_[PPL], pz_[PPL];
         float tau[PPL][C], dt[PPL][C], dp[PPL][3];
         bool live[PPL];
@@ -976,7 +982,7 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
             known[k] = kn1[k];
-            live[k] = index(c, k) < n;
+            live[k] = (int64_t)index(c, k) < n;
             px_[k] = nx[k];
             py_[k] = ny[k];
             pz_[k] = nz[k];
@@ -987,11 +993,11 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
             dp[k][0] = dp[k][1] = dp[k][2] = 0.f;
             kn1[k] = kn2[k];
         }
-        if (c + 2 < m.c1) {
+        if (c + 2 < cb1) {
 #pragma unroll
             for (int k = 0; k < PPL; ++k) kn2[k] = bits(c + 2, k);
         }
-        if (kEarlyFetch && c + 1 < m.c1) fetch(c + 1);
+        if (kEarlyFetch && c + 1 < cb1) fetch(c + 1);
         if (OPTS && (o.flags & kOptLog)) {   // logarithmic descriptors render as exp(f)
 #pragma unroll
             for (int k = 0; k < PPL; ++k)
@@ -1013,7 +1019,7 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
                 bool any = false;
 #pragma unroll
                 for (int k = 0; k < PPL; ++k) {
-                    const int64_t i = index(c, k);
+                    const uint32_t i = index(c, k);
                     const uint32_t kn = (use_vis && live[k]) ? (uint32_t)vis[(uint64_t)v * (uint64_t)n + (uint64_t)i]
                                                              : kVisUnknown;
                     point_view<C, OPTS, LN, false>(cv, L, fa, spatial_all, pack, live[k], px_[k], py_[k],
@@ -1027,7 +1033,7 @@ __global__ void __launch_bounds__(256) k_backward(const float* __restrict__ xs, 
         // features are requested only now, as a wave's loads complete in
         // issue order and loads issued before this chunk's record gathers
         // would hold up every wait on those gathers.
-        if (!kEarlyFetch && c + 1 < m.c1) fetch(c + 1);
+        if (!kEarlyFetch && c + 1 < cb1) fetch(c + 1);
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
             if (!live[k]) continue;
