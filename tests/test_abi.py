@@ -122,3 +122,8 @@ def test_scene_bind_layout(A):
     assert L.adop_scene_bind(ct.c_void_p((1 << 40) + 16), 10, 4, A.F32, ct.byref(d)) == A.E_INVALID
     assert L.adop_scene_bind(ct.c_void_p(1 << 40), 10, 0, A.F32, ct.byref(d)) == A.E_INVALID
     assert L.adop_scene_bytes(-1, 4, A.F32) == 0 and L.adop_scene_bytes(10, 4, 7) == 0
+    # point counts stop at 2^31 - 1: the point kernels number chunks and
+    # points in 32 bits, which needs (chunks * chunk size) below 2^32
+    assert L.adop_scene_bytes((1 << 31) - 1, 4, A.F32) > 0
+    assert L.adop_scene_bytes(1 << 31, 4, A.F32) == 0
+    assert L.adop_scene_bind(ct.c_void_p(1 << 40), 1 << 31, 4, A.F32, ct.byref(d)) == A.E_INVALID
